@@ -1,0 +1,203 @@
+"""Throughput of the hot path on one MI355X: RK4 DOF-steps/s, forward + adjoint.
+
+Workload (default): 40x40x20 m interior of 1 m 27-node bricks with a 5-brick
+PML (50x50x25 = 62,500 bricks, 3,093,816 state unknowns), smooth random
+lambda, mu (+-25 % about a 100 -> 250 m/s shear-velocity trend), 4 vertical
+Ricker point loads (8 Hz) solved together, 2000 RK4 steps at CFL 0.5,
+receivers at all 6,561 surface nodes of the interior.
+
+One bench step = one pass of the whole hot path on that batch: forward solve
+(6) with traces, misfit (7), adjoint solve (15) and Lame-parameter gradient
+(18).  value = n_state * nsteps * nsrc / (seconds per bench step).
+
+Usage: python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+                       [--ckpt k] [--nsteps N] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def history_nodes(prob):
+    """PML nodes that carry history (at least two axes with beta > 0)."""
+    import workloads as W
+    x, y, z = W.node_axes(prob)
+    ex, ey, ez = prob.ne_int
+    bx = np.abs(x) > 0.5 * ex * prob.h + 1e-9
+    by = np.abs(y) > 0.5 * ey * prob.h + 1e-9
+    bz = -z > ez * prob.h + 1e-9
+    cnt = (bz[:, None, None].astype(int) + by[None, :, None] + bx[None, None, :])
+    return int((cnt >= 2).sum())
+
+
+def algorithmic_bytes(cls, sizes, prob, nsrc, es):
+    """Compulsory HBM bytes of one launch of a kernel class (all sources).
+
+    nodal: per free node, stage input (6) + residual (3) + register traffic of
+    the stage mode; per PML node, stage input stresses (12, +9 on history
+    nodes) + residual (6) + register traffic; averaged over the 4 RK4 modes.
+    element kernels: stage input read once, residual rows written once,
+    materials once per launch.
+    """
+    nn = sizes.n_nodes
+    nfree = sizes.n_state - 6 * sizes.n_pml_nodes
+    nfree //= 3
+    npml = sizes.n_pml_nodes
+    nh = history_nodes(prob)
+    nint = sizes.n_int_nodes
+    if cls == "nodal":
+        # register values touched per node: (u part 6, PML part 12 + 9 on history nodes)
+        u_reg, p_reg = 6.0, 12.0 * npml + 9.0 * nh
+        modes = []
+        for reads, writes in ((1, 2), (2, 2), (1, 1), ):   # mode0: Xn | acc,Yout; mode1: Xn,acc | acc,Yout; mode2: acc | Xn
+            modes.append((reads + writes) * (u_reg * nfree + p_reg))
+        reg = (modes[0] + 2 * modes[1] + modes[2]) / 4.0
+        common = (6 + 3 + 3) * nfree + (12 + 6 + 6) * npml + (9 + 3) * nh
+        return es * nsrc * (reg + common) + es * nn
+    if cls in ("interior", "interior_adj"):
+        b = es * nsrc * (3 * nint + 3 * nint) + es * 2 * nint
+        if cls == "interior_adj":
+            b += es * nsrc * 3 * nint + 8 * 2 * 2 * nint
+        return b
+    if cls in ("pml", "pml_adj"):
+        pml_free = npml - (nn - nfree)
+        return es * nsrc * (6 * pml_free + 12 * npml + 9 * nh + 3 * pml_free + 6 * npml)
+    raise ValueError(cls)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--ckpt", type=int, default=0)
+    ap.add_argument("--nsteps", type=int, default=2000)
+    ap.add_argument("--timing-stride", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path (source-parallel gradient "
+              "all-reduce or slab decomposition) is a design, not a build; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1504_08340_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = P.FWI_FP32 if args.precision == "fp32" else P.FWI_FP64
+    es = 4 if prec == P.FWI_FP32 else 8
+    wl = W.config2(nsteps=args.nsteps)
+    prob = wl.prob
+    t0 = time.time()
+    S = P.Solver(prob, wl.src_node, wl.src_dir, wl.rec_node, precision=prec, ckpt_every=args.ckpt)
+    rho, lam, mu, wav = (S.tensor(a) for a in (wl.rho, wl.lam, wl.mu, wl.wavelet))
+    # observed data: traces of the unperturbed trend model (setup, untimed)
+    lam_t, mu_t = S.tensor(wl.lam_true), S.tensor(wl.mu_true)
+    obs = S.forward(rho, lam_t, mu_t, wav).clone()
+    traces = S.empty_traces()
+    resid = torch.empty_like(traces)
+    J = torch.empty(1, dtype=torch.float64, device=S.device)
+    gl = torch.empty(S.sizes.n_int_nodes, dtype=torch.float64, device=S.device)
+    gm = torch.empty_like(gl)
+    torch.cuda.synchronize()
+    print(f"# setup {time.time() - t0:.1f} s, workspace {S.sizes.workspace_bytes / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
+
+    def one_step():
+        S.forward(rho, lam, mu, wav, traces)
+        S.misfit(traces, obs, resid, J)
+        S.adjoint_gradient(rho, lam, mu, wav, resid, gl, gm)
+
+    for i in range(args.warmup):
+        one_step()
+        torch.cuda.synchronize()
+        print(f"# warmup step {i} done", file=sys.stderr, flush=True)
+    P.fwi_timing_enable(S.plan, args.timing_stride)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step()
+        print(f"# timed step {i} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1000.0 * elapsed / args.steps
+    n_state = S.sizes.n_state
+    value = n_state * prob.nsteps * wl.nsrc / (ms / 1000.0)
+
+    kstats = {}
+    for c, name in enumerate(P.KERNEL_CLASSES):
+        mean_ms, samples, launches = P.fwi_timing_read(S.plan, c)
+        if launches:
+            kstats[name] = dict(mean_ms=mean_ms, samples=samples, launches=launches,
+                                total_ms=mean_ms * launches / args.steps)
+    P.fwi_timing_enable(S.plan, 0)
+    dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
+    alg = algorithmic_bytes(dom, S.sizes, prob, wl.nsrc, es)
+    achieved = alg / (kstats[dom]["mean_ms"] * 1e-3) / 1e9
+    print("# kernel classes (per bench step): " + ", ".join(
+        f"{k}: {v['total_ms']:.1f} ms over {v['launches'] // args.steps} launches, mean {v['mean_ms']*1e3:.1f} us, "
+        f"{algorithmic_bytes(k, S.sizes, prob, wl.nsrc, es) / (v['mean_ms'] * 1e-3) / 1e9:.0f} GB/s"
+        for k, v in kstats.items()), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, n_state)
+
+    line = {
+        "metric": "RK4 DOF-steps/s fwd+adj",
+        "value": value,
+        "unit": "DOF-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == P.FWI_FP32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "40x40x20 m interior, 1 m Q2 bricks, 5-brick PML (62,500 bricks), "
+                        f"random lam/mu, 4 Ricker 8 Hz sources, {prob.nsteps} RK4 steps; "
+                        "forward + misfit + adjoint + gradient",
+            "n_state": n_state, "nsrc": wl.nsrc, "nsteps": prob.nsteps,
+            "ckpt_every": args.ckpt, "precision": args.precision,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "mean_launch_us": kstats[dom]["mean_ms"] * 1e3,
+            "algorithmic_bytes_per_launch": alg,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(wl, n_state):
+    """The FP64 oracle on a bounded sample of the same workload (host cores)."""
+    try:
+        from oracle import matfree  # noqa: F401
+    except ImportError:
+        return None
+    return matfree.bench_sample(wl, n_state)
+
+
+if __name__ == "__main__":
+    main()

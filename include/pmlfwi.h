@@ -1,0 +1,176 @@
+/* pmlfwi.h -- C ABI of the MI355X hot path of time-domain elastic FWI in
+ * PML-truncated 3D media (Fathi, Kallivokas, Poursartip, arXiv:1504.08340).
+ *
+ * What the library computes
+ *   fwi_forward          state problem: classical RK4 on the first-order form
+ *                        (6) of the semi-discrete hybrid system (5), starting
+ *                        at rest; displacement traces at surface receivers.
+ *   fwi_misfit           misfit (7) at the receivers (no regularization term):
+ *                        J = 1/2 sum_n w_n dt |u^n - u_m^n|^2, trapezoid weights
+ *                        w_0 = w_N = 1/2, else 1.
+ *   fwi_adjoint_gradient adjoint problem (15), solved as the exact reverse of
+ *                        the RK4 recurrence, and the misfit part of the
+ *                        Lame-parameter gradient (16)-(18), (C.1f)-(C.1g):
+ *                        m-bar = M~ g_mis (the vector whose dot product with a
+ *                        nodal direction is the directional derivative (27)).
+ *   fwi_apply_operator   one application of the forward or transposed spatial
+ *                        operator (test hook).
+ *
+ * Discretization: cubic 27-node bricks (quadratic spectral elements) with the
+ * 3x3x3 Legendre-Gauss-Lobatto rule for every integral; displacements on all
+ * nodes except the Dirichlet ones (outer sides and bottom, (2c)); six stress
+ * components (xx, yy, zz, yz, xz, xy) on every node of the closed PML; nodal
+ * Lame parameters on the closed interior box, carried into the PML from the
+ * nearest interface point (Sec. 3.1.3).  PML stretching alpha_s = 1 +
+ * alpha_o (xi/L)^m, beta_s = beta_o (xi/L)^m.
+ *
+ * Arrays at the boundary (all FP64 unless stated, C order, device memory
+ * unless stated):
+ *   full node grid   NX x NY x NZ, node id i + NX*(j + NY*k); NX = 2*(ex+2*ps)+1,
+ *                    NY = 2*(ey+2*ps)+1, NZ = 2*(ez+pb)+1; k = 0 at the bottom,
+ *                    k = NZ-1 the free surface z = 0.
+ *   material grid    NIX x NIY x NIZ = (2ex+1) x (2ey+1) x (2ez+1), the closed
+ *                    interior box; id jx + NIX*(jy + NIY*jz) = full node
+ *                    (jx + 2ps, jy + 2ps, jz + 2pb).
+ *   rho, lam, mu     [n_int_nodes]  (kg/m^3, Pa, Pa)
+ *   wavelet          [nsrc][2*nsteps+1]  force magnitude at t = k*dt/2
+ *   traces, observed, residual  [nsrc][nsteps+1][nrec][3]
+ *   g_lam, g_mu      [n_int_nodes]
+ *
+ * Ownership: the caller allocates every array and the workspace (size from
+ * fwi_query) and keeps them alive while work is enqueued.  A plan owns its
+ * host metadata and a few KB of device metadata (brick tiles, source and
+ * receiver tables) allocated by fwi_plan_create and released by
+ * fwi_plan_destroy.  All work is enqueued on the given stream (a hipStream_t,
+ * passed as void*; NULL is the default stream); no call synchronizes the host
+ * with the device except fwi_plan_create (one upload) and argument checks
+ * that read no device memory.
+ *
+ * Errors: every call returns fwi_status; nothing throws across the ABI.  On
+ * error no work has been enqueued (argument errors) or the HIP error is
+ * reported (FWI_ERR_HIP); fwi_last_error() gives a message for the plan.
+ * A plan is not thread-safe.
+ */
+#ifndef PMLFWI_H
+#define PMLFWI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FWI_OK = 0,
+  FWI_ERR_ARG = -1,       /* invalid argument (null pointer, bad size, bad index) */
+  FWI_ERR_SHAPE = -2,     /* mesh or time axis not representable */
+  FWI_ERR_HIP = -3,       /* a HIP runtime call or kernel launch failed */
+  FWI_ERR_STATE = -4,     /* call order violated (adjoint before forward) */
+  FWI_ERR_UNSTABLE = -5,  /* reserved: dt above the RK4 stability bound */
+  FWI_ERR_NOMEM = -6      /* host allocation failed */
+} fwi_status;
+
+typedef enum {
+  FWI_FP64 = 0,           /* state, element arithmetic and accumulation in FP64 */
+  FWI_FP32 = 1            /* state and element arithmetic in FP32; misfit and
+                             gradient time integrals accumulated in FP64 */
+} fwi_precision;
+
+typedef struct {
+  int32_t ne_int[3];      /* interior bricks (ex, ey, ez) */
+  int32_t npml_side;      /* PML bricks on +-x and +-y (ps) */
+  int32_t npml_bottom;    /* PML bricks below the interior (pb) */
+  double h;               /* brick edge [m] */
+  double dt;              /* time step [s] */
+  int32_t nsteps;         /* RK4 steps N */
+  double pml_alpha0;      /* alpha_o (Sec. 4.1: 5) */
+  double pml_beta0;       /* beta_o [1/s] (Sec. 4.1: 400) */
+  int32_t pml_m;          /* profile order m (Sec. 4.1: 2) */
+  int32_t nsrc;           /* sources, solved together */
+  int32_t nrec;           /* receivers (shared by all sources) */
+  int32_t precision;      /* fwi_precision */
+  int32_t ckpt_every;     /* 0: the forward keeps the interior displacement of
+                             every RK4 stage, the adjoint recomputes nothing;
+                             k > 0: the forward keeps the full state every k
+                             steps and the adjoint recomputes one k-step segment
+                             at a time */
+} fwi_problem;
+
+typedef struct {
+  int64_t n_nodes;        /* full grid nodes */
+  int64_t n_int_nodes;    /* material (closed interior) nodes */
+  int64_t n_pml_nodes;    /* nodes of the closed PML */
+  int64_t n_state;        /* paper's state unknowns: 3 per free node + 6 per PML node */
+  int64_t n_hist;         /* history unknowns (5b): the PML part of the state */
+  int64_t trace_len;      /* nsrc*(nsteps+1)*nrec*3 */
+  int64_t workspace_bytes;
+  int64_t register_bytes; /* one stored state (all sources) */
+} fwi_sizes;
+
+typedef struct fwi_plan fwi_plan;
+
+/* Sizes of a problem; pure host function. */
+fwi_status fwi_query(const fwi_problem* prob, fwi_sizes* out);
+
+/* Build a plan.  Host arrays (copied): src_node[nsrc] full-grid node ids of
+ * point loads (not Dirichlet nodes), src_dir[nsrc][3] load directions,
+ * rec_node[nrec] full-grid node ids of receivers (not Dirichlet nodes). */
+fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node,
+                           const double* src_dir, const int32_t* rec_node,
+                           fwi_plan** out);
+fwi_status fwi_plan_destroy(fwi_plan* plan);
+
+/* State problem (6): N RK4 steps from rest with the nodal load
+ * src_dir[s] * wavelet[s][k] at the stage times; writes traces (u at every
+ * receiver, steps 0..N) and keeps in the workspace what fwi_adjoint_gradient
+ * needs (stage displacements or checkpoints). */
+fwi_status fwi_forward(fwi_plan* plan, void* stream, const double* rho,
+                       const double* lam, const double* mu,
+                       const double* wavelet, void* workspace, double* traces);
+
+/* Misfit (7): residual = traces - observed and J (one double on the device). */
+fwi_status fwi_misfit(fwi_plan* plan, void* stream, const double* traces,
+                      const double* observed, double* residual, double* J);
+
+/* Adjoint (15) and gradient (18) with R = 0, for the residual of the last
+ * fwi_forward on the same workspace and the same rho, lam, mu, wavelet.
+ * Writes g_lam, g_mu (overwritten, summed over sources): the derivative of J
+ * with respect to the nodal values on the closed interior, from the interior
+ * bricks only (Sec. 3.1.3). */
+fwi_status fwi_adjoint_gradient(fwi_plan* plan, void* stream, const double* rho,
+                                const double* lam, const double* mu,
+                                const double* wavelet, const double* residual,
+                                void* workspace, double* g_lam, double* g_mu);
+
+/* Test hook: one application of the spatial operator to nodal fields.
+ * x0, x1, x2, out: [nsrc][9][n_nodes] (3 displacement then 6 stress
+ * components per node; entries off the unknowns are ignored / written 0).
+ * which = 0: out = -M^{-1} (G x0 + K x1 + C x2)            (forward, (5a))
+ * which = 1: out = -M^{-1} (G^T x0 + K^T x1 + C^T x2)      (transposed, (14a))
+ * where G^T acts on PML history fields. */
+fwi_status fwi_apply_operator(fwi_plan* plan, void* stream, int which,
+                              const double* rho, const double* lam,
+                              const double* mu, const double* x0,
+                              const double* x1, const double* x2,
+                              void* workspace, double* out);
+
+/* Kernel timing (measurement support).  While enabled, every stride-th launch
+ * of each kernel class is bracketed by HIP events recorded on the stream the
+ * kernel is launched on; fwi_timing_read waits for those events and returns
+ * the mean duration of the sampled launches.  stride = 0 disables and clears.
+ * Classes: FWI_K_INTERIOR (interior bricks, forward), FWI_K_PML (PML bricks,
+ * forward), FWI_K_NODAL (RK4 stage combination), FWI_K_INTERIOR_ADJ (interior
+ * bricks with gradient terms), FWI_K_PML_ADJ (PML bricks, transposed). */
+enum { FWI_K_INTERIOR = 0, FWI_K_PML = 1, FWI_K_NODAL = 2, FWI_K_INTERIOR_ADJ = 3,
+       FWI_K_PML_ADJ = 4, FWI_K_NCLASS = 5 };
+fwi_status fwi_timing_enable(fwi_plan* plan, int stride);
+fwi_status fwi_timing_read(fwi_plan* plan, int kernel_class, double* mean_ms,
+                           int64_t* samples, int64_t* launches);
+
+const char* fwi_status_string(fwi_status s);
+const char* fwi_last_error(const fwi_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMLFWI_H */

@@ -1,0 +1,16 @@
+"""MI355X-native hot path of time-domain elastic FWI in PML-truncated 3D media.
+
+Fathi, Kallivokas, Poursartip (arXiv:1504.08340): RK4 time stepping of the
+hybrid displacement / displacement-stress PML system (6), misfit (7), adjoint
+(15) and Lame-parameter gradient (18), as hand-written HIP kernels behind the
+C ABI declared in ``include/pmlfwi.h``.
+
+``binding`` is the thin ctypes layer (same names as the C entry points);
+``solver`` holds device buffers in torch tensors and calls the binding.
+"""
+from .binding import (FWI_FP32, FWI_FP64, FwiError, fwi_adjoint_gradient,  # noqa: F401
+                      fwi_apply_operator, fwi_forward, fwi_last_error, fwi_misfit,
+                      fwi_plan_create, fwi_plan_destroy, fwi_query, fwi_status_string,
+                      fwi_timing_enable, fwi_timing_read, KERNEL_CLASSES,
+                      make_problem)
+from .solver import Solver  # noqa: F401

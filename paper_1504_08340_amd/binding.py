@@ -1,0 +1,184 @@
+"""ctypes binding of libpmlfwi.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and forwards
+plain device pointers taken from torch tensors; all computation happens in
+the HIP kernels of the library.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmlfwi.so")
+
+FWI_FP64, FWI_FP32 = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_1504_08340_amd/_build.py` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class fwi_problem(ctypes.Structure):
+    _fields_ = [
+        ("ne_int", ctypes.c_int32 * 3),
+        ("npml_side", ctypes.c_int32),
+        ("npml_bottom", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("nsteps", ctypes.c_int32),
+        ("pml_alpha0", ctypes.c_double),
+        ("pml_beta0", ctypes.c_double),
+        ("pml_m", ctypes.c_int32),
+        ("nsrc", ctypes.c_int32),
+        ("nrec", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("ckpt_every", ctypes.c_int32),
+    ]
+
+
+class fwi_sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "n_nodes", "n_int_nodes", "n_pml_nodes", "n_state", "n_hist", "trace_len",
+        "workspace_bytes", "register_bytes")]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_lib.fwi_query.argtypes = [ctypes.POINTER(fwi_problem), ctypes.POINTER(fwi_sizes)]
+_lib.fwi_plan_create.argtypes = [ctypes.POINTER(fwi_problem), _P, _P, _P, ctypes.POINTER(_P)]
+_lib.fwi_plan_destroy.argtypes = [_P]
+_lib.fwi_forward.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
+_lib.fwi_misfit.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.fwi_adjoint_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.fwi_apply_operator.argtypes = [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.fwi_timing_enable.argtypes = [_P, ctypes.c_int]
+_lib.fwi_timing_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+_lib.fwi_status_string.argtypes = [ctypes.c_int]
+_lib.fwi_status_string.restype = ctypes.c_char_p
+_lib.fwi_last_error.argtypes = [_P]
+_lib.fwi_last_error.restype = ctypes.c_char_p
+for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
+           "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
+           "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_status_string", "fwi_last_error")
+KERNEL_CLASSES = ("interior", "pml", "nodal", "interior_adj", "pml_adj")
+
+
+class FwiError(RuntimeError):
+    pass
+
+
+def _check(status, plan=None, what=""):
+    if status != 0:
+        msg = _lib.fwi_status_string(status).decode()
+        if plan:
+            detail = _lib.fwi_last_error(plan).decode()
+            if detail:
+                msg += f": {detail}"
+        raise FwiError(f"{what} failed ({status}): {msg}")
+
+
+def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0):
+    """fwi_problem from a workloads.Problem-like object."""
+    p = fwi_problem()
+    p.ne_int[:] = list(prob.ne_int)
+    p.npml_side = prob.npml_side
+    p.npml_bottom = prob.npml_bottom
+    p.h = prob.h
+    p.dt = prob.dt
+    p.nsteps = prob.nsteps
+    p.pml_alpha0 = prob.pml_alpha0
+    p.pml_beta0 = prob.pml_beta0
+    p.pml_m = prob.pml_m
+    p.nsrc = nsrc
+    p.nrec = nrec
+    p.precision = precision
+    p.ckpt_every = ckpt_every
+    return p
+
+
+def fwi_query(problem: fwi_problem) -> fwi_sizes:
+    out = fwi_sizes()
+    _check(_lib.fwi_query(ctypes.byref(problem), ctypes.byref(out)), what="fwi_query")
+    return out
+
+
+def fwi_plan_create(problem: fwi_problem, src_node, src_dir, rec_node):
+    """Host numpy arrays: src_node int32 (nsrc,), src_dir float64 (nsrc,3), rec_node int32 (nrec,)."""
+    import numpy as np
+    s = np.ascontiguousarray(src_node, dtype=np.int32)
+    d = np.ascontiguousarray(src_dir, dtype=np.float64)
+    r = np.ascontiguousarray(rec_node, dtype=np.int32)
+    plan = _P()
+    _check(_lib.fwi_plan_create(ctypes.byref(problem), s.ctypes.data, d.ctypes.data,
+                                r.ctypes.data if r.size else None, ctypes.byref(plan)),
+           what="fwi_plan_create")
+    return plan
+
+
+def fwi_plan_destroy(plan):
+    _check(_lib.fwi_plan_destroy(plan), what="fwi_plan_destroy")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def fwi_forward(plan, stream, rho, lam, mu, wavelet, workspace, traces):
+    _check(_lib.fwi_forward(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu), _ptr(wavelet),
+                            _ptr(workspace), _ptr(traces)), plan, "fwi_forward")
+
+
+def fwi_misfit(plan, stream, traces, observed, residual, J):
+    _check(_lib.fwi_misfit(plan, _stream(stream), _ptr(traces), _ptr(observed), _ptr(residual),
+                           _ptr(J)), plan, "fwi_misfit")
+
+
+def fwi_adjoint_gradient(plan, stream, rho, lam, mu, wavelet, residual, workspace, g_lam, g_mu):
+    _check(_lib.fwi_adjoint_gradient(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu),
+                                     _ptr(wavelet), _ptr(residual), _ptr(workspace), _ptr(g_lam),
+                                     _ptr(g_mu)), plan, "fwi_adjoint_gradient")
+
+
+def fwi_apply_operator(plan, stream, which, rho, lam, mu, x0, x1, x2, workspace, out):
+    _check(_lib.fwi_apply_operator(plan, _stream(stream), int(which), _ptr(rho), _ptr(lam), _ptr(mu),
+                                   _ptr(x0), _ptr(x1), _ptr(x2), _ptr(workspace), _ptr(out)),
+           plan, "fwi_apply_operator")
+
+
+def fwi_timing_enable(plan, stride):
+    _check(_lib.fwi_timing_enable(plan, int(stride)), plan, "fwi_timing_enable")
+
+
+def fwi_timing_read(plan, kernel_class):
+    """(mean_ms, samples, launches) of the sampled launches of one kernel class."""
+    m = ctypes.c_double()
+    s = ctypes.c_int64()
+    n = ctypes.c_int64()
+    _check(_lib.fwi_timing_read(plan, int(kernel_class), ctypes.byref(m), ctypes.byref(s),
+                                ctypes.byref(n)), plan, "fwi_timing_read")
+    return m.value, s.value, n.value
+
+
+def fwi_status_string(status: int) -> str:
+    return _lib.fwi_status_string(status).decode()
+
+
+def fwi_last_error(plan) -> str:
+    return _lib.fwi_last_error(plan).decode()

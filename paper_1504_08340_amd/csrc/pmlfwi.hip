@@ -1,0 +1,713 @@
+// C ABI of the MI355X hot path: plan, workspace layout, forward / misfit /
+// adjoint-gradient drivers.  See include/pmlfwi.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pmlfwi.h"
+#include "kernels.h"
+
+using namespace pmlfwi;
+
+struct fwi_plan {
+  fwi_problem prob;
+  Geo g;
+  int nsrc, nrec;
+  std::vector<Tile> tiles_int, tiles_pml;
+  Tile* d_tiles_int = nullptr;
+  Tile* d_tiles_pml = nullptr;
+  int32_t* d_src = nullptr;
+  double* d_dir = nullptr;
+  int32_t* d_rec = nullptr;
+  const void* fwd_ws = nullptr;   // workspace holding the last forward's data
+  std::string err;
+  // sampled kernel timing
+  int tstride = 0;
+  long long launches[FWI_K_NCLASS] = {};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[FWI_K_NCLASS];
+  size_t ev_used[FWI_K_NCLASS] = {};
+};
+
+namespace {
+// Brackets one kernel launch with events when it is a sampled launch.
+struct TimedLaunch {
+  fwi_plan* p;
+  int cls;
+  hipStream_t st;
+  hipEvent_t stop = nullptr;
+  TimedLaunch(fwi_plan* p_, int c, hipStream_t s) : p(p_), cls(c), st(s) {
+    if (p->tstride <= 0) return;
+    const long long n = p->launches[cls]++;
+    if (n % p->tstride) return;
+    auto& v = p->ev[cls];
+    if (p->ev_used[cls] == v.size()) {
+      std::pair<hipEvent_t, hipEvent_t> e{};
+      if (hipEventCreate(&e.first) != hipSuccess || hipEventCreate(&e.second) != hipSuccess) return;
+      v.push_back(e);
+    }
+    auto& e = v[p->ev_used[cls]++];
+    (void)hipEventRecord(e.first, st);
+    stop = e.second;
+  }
+  ~TimedLaunch() {
+    if (stop) (void)hipEventRecord(stop, st);
+  }
+};
+}  // namespace
+
+namespace {
+
+constexpr int TX = 2, TY = 2, TZ = 2;   // bricks per element tile
+
+fwi_status fail(fwi_plan* p, fwi_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  return s;
+}
+
+#define HIP_TRY(plan, call)                                                   \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return fail(plan, FWI_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+Geo make_geo(const fwi_problem& P) {
+  Geo g{};
+  g.ex = P.ne_int[0]; g.ey = P.ne_int[1]; g.ez = P.ne_int[2];
+  g.ps = P.npml_side; g.pb = P.npml_bottom;
+  g.EX = g.ex + 2 * g.ps; g.EY = g.ey + 2 * g.ps; g.EZ = g.ez + g.pb;
+  g.NX = 2 * g.EX + 1; g.NY = 2 * g.EY + 1; g.NZ = 2 * g.EZ + 1;
+  g.NIX = 2 * g.ex + 1; g.NIY = 2 * g.ey + 1; g.NIZ = 2 * g.ez + 1;
+  g.w = 2 * g.ps + 1; g.zb = 2 * g.pb;
+  g.plane = g.NX * g.NY;
+  g.ring = 2 * g.w * g.NX + (g.NY - 2 * g.w) * 2 * g.w;
+  g.n_nodes = g.plane * g.NZ;
+  g.n_pml = (g.zb + 1) * g.plane + (g.NZ - g.zb - 1) * g.ring;
+  g.n_int = g.NIX * g.NIY * g.NIZ;
+  g.h = P.h;
+  g.hx = 0.5 * g.ex * P.h; g.hy = 0.5 * g.ey * P.h; g.hz = g.ez * P.h;
+  g.Lps = g.ps * P.h; g.Lpb = g.pb * P.h;
+  g.x0 = -(g.hx + g.Lps); g.y0 = -(g.hy + g.Lps); g.z0 = -(g.hz + g.Lpb);
+  g.alpha0 = P.pml_alpha0; g.beta0 = P.pml_beta0; g.m = P.pml_m;
+  return g;
+}
+
+// Per-axis brick segments: the interior range cut into chunks of T from its
+// lower end, each PML range cut into chunks of T away from the interior.
+struct Seg { int start, count; bool interior; };
+
+std::vector<Seg> axis_segments(int lo_pml, int n_int, int hi_pml, int T) {
+  std::vector<Seg> s;
+  for (int e = lo_pml; e > 0; e -= T) s.push_back({std::max(0, e - T), e - std::max(0, e - T), false});
+  for (int e = lo_pml; e < lo_pml + n_int; e += T)
+    s.push_back({e, std::min(T, lo_pml + n_int - e), true});
+  for (int e = lo_pml + n_int; e < lo_pml + n_int + hi_pml; e += T)
+    s.push_back({e, std::min(T, lo_pml + n_int + hi_pml - e), false});
+  return s;
+}
+
+void build_tiles(fwi_plan* p) {
+  const Geo& g = p->g;
+  auto sx = axis_segments(g.ps, g.ex, g.ps, TX);
+  auto sy = axis_segments(g.ps, g.ey, g.ps, TY);
+  auto sz = axis_segments(g.pb, g.ez, 0, TZ);
+  for (auto& c : sz)
+    for (auto& b : sy)
+      for (auto& a : sx) {
+        Tile t{a.start, b.start, c.start, a.count | (b.count << 8) | (c.count << 16)};
+        if (a.interior && b.interior && c.interior) p->tiles_int.push_back(t);
+        else p->tiles_pml.push_back(t);
+      }
+}
+
+// ---------------------------------------------------------------- sizes
+struct Layout {
+  size_t es;          // element size of the state type
+  size_t reg_elems;   // one register, one source
+  size_t res_elems;   // residual, one source
+  size_t stage_elems; // stored stage displacement, all sources
+  int nreg, nstore, nckpt;
+  size_t off_lam, off_mu, off_invm, off_regs, off_res, off_store, off_ckpt, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout(const fwi_problem& P, const Geo& g) {
+  Layout L{};
+  L.es = P.precision == FWI_FP32 ? 4 : 8;
+  L.reg_elems = (size_t)U_NCOMP * g.n_nodes + (size_t)P_NCOMP * g.n_pml;
+  L.res_elems = 3 * (size_t)g.n_nodes + 6 * (size_t)g.n_pml;
+  L.stage_elems = (size_t)P.nsrc * 3 * g.n_int;
+  const int k = P.ckpt_every;
+  L.nreg = k == 0 ? 4 : 8;
+  L.nstore = k == 0 ? P.nsteps : std::min(k, P.nsteps);
+  L.nckpt = k == 0 ? 0 : (P.nsteps + k - 1) / k;
+  size_t o = 0;
+  L.off_lam = o; o = align256(o + (size_t)g.n_int * L.es);
+  L.off_mu = o; o = align256(o + (size_t)g.n_int * L.es);
+  L.off_invm = o; o = align256(o + (size_t)g.n_nodes * L.es);
+  L.off_regs = o; o = align256(o + (size_t)L.nreg * P.nsrc * L.reg_elems * L.es);
+  L.off_res = o; o = align256(o + (size_t)P.nsrc * L.res_elems * L.es);
+  L.off_store = o; o = align256(o + (size_t)L.nstore * 4 * L.stage_elems * L.es);
+  L.off_ckpt = o; o = align256(o + (size_t)L.nckpt * P.nsrc * L.reg_elems * L.es);
+  L.total = o;
+  return L;
+}
+
+fwi_status validate(const fwi_problem* P) {
+  if (!P) return FWI_ERR_ARG;
+  for (int d = 0; d < 3; ++d)
+    if (P->ne_int[d] < 1) return FWI_ERR_SHAPE;
+  if (P->npml_side < 1 || P->npml_bottom < 1) return FWI_ERR_SHAPE;
+  if (!(P->h > 0) || !(P->dt > 0) || P->nsteps < 1) return FWI_ERR_ARG;
+  if (P->nsrc < 1 || P->nrec < 0 || P->pml_m < 0 || P->ckpt_every < 0) return FWI_ERR_ARG;
+  if (P->precision != FWI_FP64 && P->precision != FWI_FP32) return FWI_ERR_ARG;
+  const double nx = 2.0 * (P->ne_int[0] + 2.0 * P->npml_side) + 1;
+  const double ny = 2.0 * (P->ne_int[1] + 2.0 * P->npml_side) + 1;
+  const double nz = 2.0 * (P->ne_int[2] + P->npml_bottom) + 1;
+  if (nx * ny * nz * 21.0 > 2147483647.0) return FWI_ERR_SHAPE;   // 32-bit node indexing
+  return FWI_OK;
+}
+
+// ---------------------------------------------------------------- small kernels
+template <typename T>
+__global__ void fill_kernel(T* p, size_t n, T v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename R>
+__global__ void convert_kernel(const double* __restrict__ in, R* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = R(in[i]);
+}
+
+template <typename R>
+__global__ void receivers_kernel(const R* __restrict__ X, long long reg, int n_nodes,
+                                 const int* __restrict__ rec, int nrec, double* __restrict__ traces,
+                                 int step, int nsteps) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (r >= nrec) return;
+  const R* U = X + (size_t)src * reg;
+  double* T = traces + ((size_t)src * (nsteps + 1) + step) * nrec * 3 + (size_t)r * 3;
+  const int node = rec[r];
+  for (int d = 0; d < 3; ++d) T[d] = (double)U[(size_t)d * n_nodes + node];
+}
+
+// Adjoint impulse after a reverse step: y2_u += M^{-1} dt w_n (u^n - u_m^n) at receivers.
+template <typename R>
+__global__ void impulse_kernel(R* __restrict__ Y, long long reg, int n_nodes, const R* __restrict__ invMu,
+                               const int* __restrict__ rec, int nrec, const double* __restrict__ resid,
+                               int step, int nsteps, double scale) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (r >= nrec) return;
+  R* U = Y + (size_t)src * reg;
+  const double* E = resid + ((size_t)src * (nsteps + 1) + step) * nrec * 3 + (size_t)r * 3;
+  const int node = rec[r];
+  const R im = invMu[node];
+  for (int d = 0; d < 3; ++d) atomic_add(&U[(size_t)(3 + d) * n_nodes + node], R(scale * E[d]) * im);
+}
+
+__global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ obs,
+                              double* __restrict__ resid, long long n, int per_step, int nsteps,
+                              double half_dt, double* __restrict__ J) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double r = tr[i] - obs[i];
+    resid[i] = r;
+    const int step = (int)((i / per_step) % (nsteps + 1));
+    const double w = (step == 0 || step == nsteps) ? 0.5 : 1.0;
+    acc += w * r * r;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(J, half_dt * part[0]);
+}
+
+// x1 displacement of a register on the interior closure -> stage store slot.
+template <typename R>
+__global__ void extract_kernel(Geo g, const R* __restrict__ X, long long reg, R* __restrict__ S, long long sstr) {
+  const int mi = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (mi >= g.n_int) return;
+  const int jz = mi / (g.NIX * g.NIY), rr = mi - jz * g.NIX * g.NIY, jy = rr / g.NIX, jx = rr - jy * g.NIX;
+  const size_t node = (size_t)(jx + 2 * g.ps) + (size_t)g.NX * ((jy + 2 * g.ps) + (size_t)g.NY * (jz + 2 * g.pb));
+  for (int d = 0; d < 3; ++d)
+    S[(size_t)src * sstr + (size_t)d * g.n_int + mi] = X[(size_t)src * reg + (size_t)d * g.n_nodes + node];
+}
+
+// Nodal test fields [nsrc][9][n_nodes] <-> register slot (0: x0, 1: x1, 2: x2).
+template <typename R>
+__global__ void pack_kernel(Geo g, const double* __restrict__ in, R* __restrict__ X, long long reg, int slot) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (node >= g.n_nodes) return;
+  const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
+  const size_t nn = g.n_nodes, np = g.n_pml;
+  const double* F = in + (size_t)src * 9 * nn;
+  R* U = X + (size_t)src * reg;
+  R* P = U + 6 * nn;
+  const bool dir = is_dirichlet(g, i, j, k), pml = in_pml(g, i, j, k);
+  const size_t p = pml ? (size_t)pml_index(g, i, j, k) : 0;
+  for (int d = 0; d < 3; ++d) {
+    const R v = dir ? R(0) : R(F[d * nn + node]);
+    if (slot == 0) { if (pml) P[(P_X0U + d) * np + p] = v; }
+    else U[(size_t)(slot == 1 ? d : 3 + d) * nn + node] = v;
+  }
+  if (pml) {
+    const int base = slot == 0 ? P_X0S : (slot == 1 ? P_X1S : P_X2S);
+    for (int v = 0; v < 6; ++v) P[(base + v) * np + p] = R(F[(3 + v) * nn + node]);
+  }
+}
+
+// out = -M^{-1}(r + nodal PML terms) for the register Y, nodal layout.
+template <typename R>
+__global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, const R* __restrict__ res,
+                             long long rstr, const R* __restrict__ invMu, double* __restrict__ out) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (node >= g.n_nodes) return;
+  const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
+  const size_t nn = g.n_nodes, np = g.n_pml;
+  const R* U = Y + (size_t)src * reg;
+  const R* P = U + 6 * nn;
+  const R* rs = res + (size_t)src * rstr;
+  double* O = out + (size_t)src * 9 * nn;
+  const bool dir = is_dirichlet(g, i, j, k), pml = in_pml(g, i, j, k);
+  for (int c = 0; c < 9; ++c) O[c * nn + node] = 0.0;
+  double mrd, mp;
+  lumped_masses(g, i, j, k, mrd, mp);
+  const PmlCoef cf = pml_coef(g, i, j, k);
+  const size_t p = pml ? (size_t)pml_index(g, i, j, k) : 0;
+  const bool hist = cf.nbeta >= 2;
+  if (!dir) {
+    for (int d = 0; d < 3; ++d) {
+      double a = -(double)invMu[node] * (double)rs[d * nn + node];
+      if (pml) {
+        const double kap = mp / (mrd + cf.a * mp);
+        const double u0 = hist ? (double)P[(P_X0U + d) * np + p] : 0.0;
+        a -= kap * (cf.b * (double)U[(3 + d) * nn + node] + cf.c * (double)U[d * nn + node] + cf.d * u0);
+      }
+      O[d * nn + node] = a;
+    }
+  }
+  if (pml) {
+    for (int v = 0; v < 6; ++v) {
+      const double s0 = hist ? (double)P[(P_X0S + v) * np + p] : 0.0;
+      O[(3 + v) * nn + node] = -(double)rs[3 * nn + v * np + p] / (cf.a * mp) -
+                               (cf.b * (double)P[(P_X2S + v) * np + p] + cf.c * (double)P[(P_X1S + v) * np + p] +
+                                cf.d * s0) / cf.a;
+    }
+  }
+}
+
+inline unsigned blocks(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------- driver
+template <typename R>
+struct Run {
+  fwi_plan* p;
+  hipStream_t st;
+  Layout L;
+  char* ws;
+  const Geo& g() const { return p->g; }
+  R* lam() const { return (R*)(ws + L.off_lam); }
+  R* mu() const { return (R*)(ws + L.off_mu); }
+  R* invm() const { return (R*)(ws + L.off_invm); }
+  R* reg(int r) const { return (R*)(ws + L.off_regs) + (size_t)r * p->nsrc * L.reg_elems; }
+  R* res() const { return (R*)(ws + L.off_res); }
+  R* store(int nl, int s) const {
+    return (R*)(ws + L.off_store) + ((size_t)nl * 4 + s) * L.stage_elems;
+  }
+  R* ckpt(int c) const { return (R*)(ws + L.off_ckpt) + (size_t)c * p->nsrc * L.reg_elems; }
+
+  template <typename T>
+  fwi_status fill(T* ptr, size_t n, T v) {
+    if (n == 0) return FWI_OK;
+    const unsigned nb = std::min<size_t>(blocks(n, 256), 65536);
+    fill_kernel<T><<<nb, 256, 0, st>>>(ptr, n, v);
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  fwi_status setup(const double* rho, const double* lam, const double* mu) {
+    const Geo& G = g();
+    convert_kernel<R><<<blocks(G.n_int, 256), 256, 0, st>>>(lam, this->lam(), G.n_int);
+    convert_kernel<R><<<blocks(G.n_int, 256), 256, 0, st>>>(mu, this->mu(), G.n_int);
+    inv_mass_kernel<R><<<blocks(G.n_nodes, 256), 256, 0, st>>>(G, rho, invm());
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw, double* gl, double* gm) {
+    const Geo& G = g();
+    const long long reg = (long long)L.reg_elems, rs = (long long)L.res_elems;
+    if (!p->tiles_int.empty()) {
+      dim3 grid((unsigned)p->tiles_int.size(), p->nsrc);
+      TimedLaunch tl(p, fwd ? FWI_K_INTERIOR_ADJ : FWI_K_INTERIOR, st);
+      if (fwd)
+        interior_element_kernel<R, TX, TY, TZ, true><<<grid, 128, 0, st>>>(
+            G, p->d_tiles_int, Y, reg, lam(), mu(), res(), rs, fwd, 3LL * G.n_int, gw, gl, gm);
+      else
+        interior_element_kernel<R, TX, TY, TZ, false><<<grid, 128, 0, st>>>(
+            G, p->d_tiles_int, Y, reg, lam(), mu(), res(), rs, nullptr, 0, 0.0, nullptr, nullptr);
+    }
+    if (!p->tiles_pml.empty()) {
+      dim3 grid((unsigned)p->tiles_pml.size(), p->nsrc);
+      TimedLaunch tl(p, adj ? FWI_K_PML_ADJ : FWI_K_PML, st);
+      if (adj)
+        pml_element_kernel<R, TX, TY, TZ, true><<<grid, 128, 0, st>>>(G, p->d_tiles_pml, Y, reg, lam(), mu(), res(), rs);
+      else
+        pml_element_kernel<R, TX, TY, TZ, false><<<grid, 128, 0, st>>>(G, p->d_tiles_pml, Y, reg, lam(), mu(), res(), rs);
+    }
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  fwi_status nodal(int s, R* Yin, R* Yout, R* Xn, R* acc, const double* wav, int step, R* store) {
+    static const double cA[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+    static const double cY[4] = {0.5, 0.5, 1.0, 0.0};
+    static const int toff[4] = {0, 1, 1, 2};
+    const Geo& G = g();
+    const double dt = p->prob.dt;
+    NodalArgs<R> A{};
+    A.Yin = Yin; A.Yout = Yout; A.Xn = Xn; A.acc = acc; A.res = res(); A.invMu = invm();
+    A.reg = (long long)L.reg_elems; A.rstr = (long long)L.res_elems;
+    A.cA = R(cA[s] * dt); A.cY = R(cY[s] * dt);
+    A.mode = s == 0 ? 0 : (s == 3 ? 2 : 1);
+    if (wav) {
+      A.src_node = p->d_src; A.src_dir = p->d_dir; A.wav = wav;
+      A.wav_len = 2 * p->prob.nsteps + 1; A.wav_idx = 2 * step + toff[s];
+    }
+    A.store = store; A.store_stride = 3LL * G.n_int;
+    dim3 grid(blocks((size_t)G.n_nodes + G.n_pml, 256), p->nsrc);
+    {
+      TimedLaunch tl(p, FWI_K_NODAL, st);
+      nodal_rk_kernel<R><<<grid, 256, 0, st>>>(G, A);
+    }
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  // One RK4 step on (Xn, Ya, Yb, acc); `store_nl` >= 0 writes the stage
+  // displacements of this step to store slot store_nl (and the next step's
+  // first stage to store_nl+1 when store_next).
+  fwi_status step(bool adj, int r0, int n, const double* wav, int store_nl, bool store_next,
+                  int fwd_nl, double* gl, double* gm) {
+    static const double bw[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+    R* Xn = reg(r0);
+    R* Ya = reg(r0 + 1);
+    R* Yb = reg(r0 + 2);
+    R* acc = reg(r0 + 3);
+    R* in = Xn;
+    R* outs[4] = {Ya, Yb, Ya, nullptr};
+    for (int s = 0; s < 4; ++s) {
+      const R* fwd = fwd_nl >= 0 ? store(fwd_nl, 3 - s) : nullptr;
+      fwi_status e = elements(adj, in, fwd, -bw[s] * p->prob.dt, gl, gm);
+      if (e != FWI_OK) return e;
+      R* st_ = nullptr;
+      if (store_nl >= 0) {
+        if (s < 3) st_ = store(store_nl, s + 1);
+        else if (store_next) st_ = store(store_nl + 1, 0);
+      }
+      e = nodal(s, in, outs[s], Xn, acc, wav, n, st_);
+      if (e != FWI_OK) return e;
+      in = outs[s];
+    }
+    return FWI_OK;
+  }
+
+  fwi_status zero_regs(int r0, int nr) {
+    fwi_status e = fill<R>(reg(r0), (size_t)nr * p->nsrc * L.reg_elems, R(0));
+    if (e != FWI_OK) return e;
+    return fill<R>(res(), (size_t)p->nsrc * L.res_elems, R(0));
+  }
+
+  fwi_status extract(const R* X, R* S) {
+    const Geo& G = g();
+    extract_kernel<R><<<dim3(blocks(G.n_int, 256), p->nsrc), 256, 0, st>>>(G, X, (long long)L.reg_elems, S, 3LL * G.n_int);
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  fwi_status forward(const double* rho, const double* lam_, const double* mu_, const double* wav,
+                     double* traces) {
+    const fwi_problem& P = p->prob;
+    fwi_status e;
+    if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
+    if ((e = zero_regs(0, 4)) != FWI_OK) return e;
+    const size_t tl = (size_t)P.nsrc * (P.nsteps + 1) * p->nrec * 3;
+    if ((e = fill<double>(traces, tl, 0.0)) != FWI_OK) return e;
+    const bool keep_all = P.ckpt_every == 0;
+    if (keep_all && (e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
+    for (int n = 0; n < P.nsteps; ++n) {
+      if (!keep_all && n % P.ckpt_every == 0)
+        HIP_TRY(p, hipMemcpyAsync(ckpt(n / P.ckpt_every), reg(0), (size_t)P.nsrc * L.reg_elems * L.es,
+                                  hipMemcpyDeviceToDevice, st));
+      if ((e = step(false, 0, n, wav, keep_all ? n : -1, n + 1 < P.nsteps, -1, nullptr, nullptr)) != FWI_OK)
+        return e;
+      if (p->nrec > 0) {
+        receivers_kernel<R><<<dim3(blocks(p->nrec, 128), P.nsrc), 128, 0, st>>>(
+            reg(0), (long long)L.reg_elems, g().n_nodes, p->d_rec, p->nrec, traces, n + 1, P.nsteps);
+        HIP_TRY(p, hipGetLastError());
+      }
+    }
+    return FWI_OK;
+  }
+
+  fwi_status impulse(int r0, const double* resid, int n) {
+    if (p->nrec == 0) return FWI_OK;
+    const fwi_problem& P = p->prob;
+    const double w = (n == 0 || n == P.nsteps) ? 0.5 : 1.0;
+    impulse_kernel<R><<<dim3(blocks(p->nrec, 128), P.nsrc), 128, 0, st>>>(
+        reg(r0), (long long)L.reg_elems, g().n_nodes, invm(), p->d_rec, p->nrec, resid, n, P.nsteps, P.dt * w);
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  fwi_status adjoint(const double* rho, const double* lam_, const double* mu_, const double* wav,
+                     const double* resid, double* gl, double* gm) {
+    const fwi_problem& P = p->prob;
+    const Geo& G = g();
+    fwi_status e;
+    if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
+    if ((e = fill<double>(gl, G.n_int, 0.0)) != FWI_OK) return e;
+    if ((e = fill<double>(gm, G.n_int, 0.0)) != FWI_OK) return e;
+    const bool keep_all = P.ckpt_every == 0;
+    const int ra = keep_all ? 0 : 4;          // adjoint registers
+    if ((e = zero_regs(ra, 4)) != FWI_OK) return e;
+    if ((e = impulse(ra, resid, P.nsteps)) != FWI_OK) return e;
+    const int k = keep_all ? P.nsteps : P.ckpt_every;
+    const int nseg = (P.nsteps + k - 1) / k;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int a = sg * k, b = std::min(P.nsteps, a + k);
+      if (!keep_all) {
+        HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(sg), (size_t)P.nsrc * L.reg_elems * L.es,
+                                  hipMemcpyDeviceToDevice, st));
+        if ((e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
+        for (int n = a; n < b; ++n)
+          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1, nullptr, nullptr)) != FWI_OK) return e;
+      }
+      for (int n = b - 1; n >= a; --n) {
+        if ((e = step(true, ra, n, nullptr, -1, false, n - a, gl, gm)) != FWI_OK) return e;
+        if (n > 0 && (e = impulse(ra, resid, n)) != FWI_OK) return e;
+      }
+    }
+    return FWI_OK;
+  }
+
+  fwi_status apply(int which, const double* rho, const double* lam_, const double* mu_, const double* x0,
+                   const double* x1, const double* x2, double* out) {
+    const Geo& G = g();
+    fwi_status e;
+    if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
+    if ((e = zero_regs(0, 1)) != FWI_OK) return e;
+    const double* xs[3] = {x0, x1, x2};
+    for (int s = 0; s < 3; ++s) {
+      pack_kernel<R><<<dim3(blocks(G.n_nodes, 256), p->nsrc), 256, 0, st>>>(G, xs[s], reg(0), (long long)L.reg_elems, s);
+      HIP_TRY(p, hipGetLastError());
+    }
+    if ((e = elements(which == 1, reg(0), nullptr, 0.0, nullptr, nullptr)) != FWI_OK) return e;
+    accel_kernel<R><<<dim3(blocks(G.n_nodes, 256), p->nsrc), 256, 0, st>>>(G, reg(0), (long long)L.reg_elems, res(),
+                                                                          (long long)L.res_elems, invm(), out);
+    HIP_TRY(p, hipGetLastError());
+    return fill<R>(res(), (size_t)p->nsrc * L.res_elems, R(0));
+  }
+};
+
+template <typename F>
+fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f) {
+  Layout L = layout(p->prob, p->g);
+  if (p->prob.precision == FWI_FP32) {
+    Run<float> r{p, st, L, (char*)ws};
+    return f(r);
+  }
+  Run<double> r{p, st, L, (char*)ws};
+  return f(r);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+fwi_status fwi_query(const fwi_problem* prob, fwi_sizes* out) {
+  if (!prob || !out) return FWI_ERR_ARG;
+  fwi_status v = validate(prob);
+  if (v != FWI_OK) return v;
+  const Geo g = make_geo(*prob);
+  const Layout L = layout(*prob, g);
+  const int64_t free_nodes = (int64_t)(g.NX - 2) * (g.NY - 2) * (g.NZ - 1);
+  const int64_t dir_nodes = (int64_t)g.n_nodes - free_nodes;
+  out->n_nodes = g.n_nodes;
+  out->n_int_nodes = g.n_int;
+  out->n_pml_nodes = g.n_pml;
+  out->n_state = 3 * free_nodes + 6 * (int64_t)g.n_pml;
+  out->n_hist = 3 * ((int64_t)g.n_pml - dir_nodes) + 6 * (int64_t)g.n_pml;
+  out->trace_len = (int64_t)prob->nsrc * (prob->nsteps + 1) * prob->nrec * 3;
+  out->workspace_bytes = (int64_t)L.total;
+  out->register_bytes = (int64_t)(prob->nsrc * L.reg_elems * L.es);
+  return FWI_OK;
+}
+
+fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, const double* src_dir,
+                           const int32_t* rec_node, fwi_plan** out) {
+  if (!out) return FWI_ERR_ARG;
+  *out = nullptr;
+  fwi_status v = validate(prob);
+  if (v != FWI_OK) return v;
+  if (!src_node || !src_dir || (prob->nrec > 0 && !rec_node)) return FWI_ERR_ARG;
+  fwi_plan* p = new (std::nothrow) fwi_plan();
+  if (!p) return FWI_ERR_NOMEM;
+  p->prob = *prob;
+  p->g = make_geo(*prob);
+  p->nsrc = prob->nsrc;
+  p->nrec = prob->nrec;
+  const Geo& g = p->g;
+  auto bad_node = [&](int32_t id) {
+    if (id < 0 || id >= g.n_nodes) return true;
+    const int k = id / g.plane, r = id - k * g.plane, j = r / g.NX, i = r - j * g.NX;
+    return is_dirichlet(g, i, j, k);
+  };
+  for (int s = 0; s < prob->nsrc; ++s)
+    if (bad_node(src_node[s])) { delete p; return FWI_ERR_ARG; }
+  for (int r = 0; r < prob->nrec; ++r)
+    if (bad_node(rec_node[r])) { delete p; return FWI_ERR_ARG; }
+  build_tiles(p);
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up((void**)&p->d_tiles_int, p->tiles_int.data(), p->tiles_int.size() * sizeof(Tile));
+  if (e == hipSuccess) e = up((void**)&p->d_tiles_pml, p->tiles_pml.data(), p->tiles_pml.size() * sizeof(Tile));
+  if (e == hipSuccess) e = up((void**)&p->d_src, src_node, prob->nsrc * sizeof(int32_t));
+  if (e == hipSuccess) e = up((void**)&p->d_dir, src_dir, prob->nsrc * 3 * sizeof(double));
+  if (e == hipSuccess) e = up((void**)&p->d_rec, rec_node, prob->nrec * sizeof(int32_t));
+  if (e != hipSuccess) {
+    fwi_plan_destroy(p);
+    return FWI_ERR_HIP;
+  }
+  *out = p;
+  return FWI_OK;
+}
+
+fwi_status fwi_timing_enable(fwi_plan* p, int stride) {
+  if (!p || stride < 0) return FWI_ERR_ARG;
+  p->tstride = stride;
+  for (int c = 0; c < FWI_K_NCLASS; ++c) {
+    p->launches[c] = 0;
+    p->ev_used[c] = 0;
+  }
+  return FWI_OK;
+}
+
+fwi_status fwi_timing_read(fwi_plan* p, int cls, double* mean_ms, int64_t* samples, int64_t* launches) {
+  if (!p || cls < 0 || cls >= FWI_K_NCLASS || !mean_ms || !samples || !launches) return FWI_ERR_ARG;
+  double tot = 0.0;
+  for (size_t i = 0; i < p->ev_used[cls]; ++i) {
+    auto& e = p->ev[cls][i];
+    HIP_TRY(p, hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIP_TRY(p, hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+  }
+  *samples = (int64_t)p->ev_used[cls];
+  *launches = p->launches[cls];
+  *mean_ms = p->ev_used[cls] ? tot / p->ev_used[cls] : 0.0;
+  return FWI_OK;
+}
+
+fwi_status fwi_plan_destroy(fwi_plan* p) {
+  if (!p) return FWI_ERR_ARG;
+  for (auto& v : p->ev)
+    for (auto& e : v) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  (void)hipFree(p->d_tiles_int);
+  (void)hipFree(p->d_tiles_pml);
+  (void)hipFree(p->d_src);
+  (void)hipFree(p->d_dir);
+  (void)hipFree(p->d_rec);
+  delete p;
+  return FWI_OK;
+}
+
+fwi_status fwi_forward(fwi_plan* p, void* stream, const double* rho, const double* lam, const double* mu,
+                       const double* wavelet, void* workspace, double* traces) {
+  if (!p) return FWI_ERR_ARG;
+  if (!rho || !lam || !mu || !wavelet || !workspace || (p->nrec > 0 && !traces))
+    return fail(p, FWI_ERR_ARG, "fwi_forward: null pointer");
+  p->fwd_ws = nullptr;
+  fwi_status s = dispatch(p, (hipStream_t)stream, workspace,
+                          [&](auto& r) { return r.forward(rho, lam, mu, wavelet, traces); });
+  if (s == FWI_OK) p->fwd_ws = workspace;
+  return s;
+}
+
+fwi_status fwi_misfit(fwi_plan* p, void* stream, const double* traces, const double* observed, double* residual,
+                      double* J) {
+  if (!p) return FWI_ERR_ARG;
+  if (!traces || !observed || !residual || !J) return fail(p, FWI_ERR_ARG, "fwi_misfit: null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  fill_kernel<double><<<1, 32, 0, st>>>(J, 1, 0.0);
+  const long long n = (long long)p->nsrc * (p->prob.nsteps + 1) * p->nrec * 3;
+  if (n > 0) {
+    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 2048);
+    misfit_kernel<<<nb, 256, 0, st>>>(traces, observed, residual, n, p->nrec * 3, p->prob.nsteps,
+                                      0.5 * p->prob.dt, J);
+  }
+  HIP_TRY(p, hipGetLastError());
+  return FWI_OK;
+}
+
+fwi_status fwi_adjoint_gradient(fwi_plan* p, void* stream, const double* rho, const double* lam,
+                                const double* mu, const double* wavelet, const double* residual,
+                                void* workspace, double* g_lam, double* g_mu) {
+  if (!p) return FWI_ERR_ARG;
+  if (!rho || !lam || !mu || !wavelet || !workspace || !g_lam || !g_mu || (p->nrec > 0 && !residual))
+    return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient: null pointer");
+  if (p->fwd_ws != workspace)
+    return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient: no fwi_forward on this workspace");
+  return dispatch(p, (hipStream_t)stream, workspace,
+                  [&](auto& r) { return r.adjoint(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
+}
+
+fwi_status fwi_apply_operator(fwi_plan* p, void* stream, int which, const double* rho, const double* lam,
+                              const double* mu, const double* x0, const double* x1, const double* x2,
+                              void* workspace, double* out) {
+  if (!p) return FWI_ERR_ARG;
+  if (which != 0 && which != 1) return fail(p, FWI_ERR_ARG, "fwi_apply_operator: which must be 0 or 1");
+  if (!rho || !lam || !mu || !x0 || !x1 || !x2 || !workspace || !out)
+    return fail(p, FWI_ERR_ARG, "fwi_apply_operator: null pointer");
+  p->fwd_ws = nullptr;   // the hook reuses the forward registers
+  return dispatch(p, (hipStream_t)stream, workspace,
+                  [&](auto& r) { return r.apply(which, rho, lam, mu, x0, x1, x2, out); });
+}
+
+const char* fwi_status_string(fwi_status s) {
+  switch (s) {
+    case FWI_OK: return "ok";
+    case FWI_ERR_ARG: return "invalid argument";
+    case FWI_ERR_SHAPE: return "unsupported mesh or time axis";
+    case FWI_ERR_HIP: return "HIP runtime error";
+    case FWI_ERR_STATE: return "call order violated";
+    case FWI_ERR_UNSTABLE: return "time step above the stability bound";
+    case FWI_ERR_NOMEM: return "out of host memory";
+  }
+  return "unknown status";
+}
+
+const char* fwi_last_error(const fwi_plan* p) { return p ? p->err.c_str() : "no plan"; }
+
+}  // extern "C"

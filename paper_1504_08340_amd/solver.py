@@ -1,0 +1,81 @@
+"""Device buffers for one problem, held in torch tensors, and calls into the C ABI.
+
+Nothing here computes: the tensors are allocated with torch (memory and
+streams only) and every step of the method runs in libpmlfwi.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class Solver:
+    """One plan + workspace on a CUDA/HIP device.
+
+    Parameters mirror ``fwi_problem``; ``prob`` is any object with the fields
+    of ``workloads.Problem`` (ne_int, npml_side, npml_bottom, h, dt, nsteps,
+    pml_alpha0, pml_beta0, pml_m).
+    """
+
+    def __init__(self, prob, src_node, src_dir, rec_node, precision=B.FWI_FP64,
+                 ckpt_every=0, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a GPU (HIP device); no CPU fallback exists")
+        self.device = torch.device(device)
+        self.nsrc = int(len(src_node))
+        self.nrec = int(len(rec_node))
+        self.problem = B.make_problem(prob, self.nsrc, self.nrec, precision, ckpt_every)
+        self.sizes = B.fwi_query(self.problem)
+        self.nsteps = prob.nsteps
+        self.plan = B.fwi_plan_create(self.problem, np.asarray(src_node), np.asarray(src_dir),
+                                      np.asarray(rec_node))
+        nbytes = int(self.sizes.workspace_bytes)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        self.trace_shape = (self.nsrc, self.nsteps + 1, self.nrec, 3)
+
+    def close(self):
+        if self.plan is not None:
+            B.fwi_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    def tensor(self, a, dtype=torch.float64):
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=self.device)
+
+    def empty_traces(self):
+        return torch.empty(self.trace_shape, dtype=torch.float64, device=self.device)
+
+    # -- C ABI calls -------------------------------------------------------
+    def forward(self, rho, lam, mu, wavelet, traces=None, stream=None):
+        traces = self.empty_traces() if traces is None else traces
+        B.fwi_forward(self.plan, stream, rho, lam, mu, wavelet, self.workspace, traces)
+        return traces
+
+    def misfit(self, traces, observed, residual=None, J=None, stream=None):
+        residual = torch.empty_like(traces) if residual is None else residual
+        J = torch.empty(1, dtype=torch.float64, device=self.device) if J is None else J
+        B.fwi_misfit(self.plan, stream, traces, observed, residual, J)
+        return J, residual
+
+    def adjoint_gradient(self, rho, lam, mu, wavelet, residual, g_lam=None, g_mu=None, stream=None):
+        n = int(self.sizes.n_int_nodes)
+        g_lam = torch.empty(n, dtype=torch.float64, device=self.device) if g_lam is None else g_lam
+        g_mu = torch.empty(n, dtype=torch.float64, device=self.device) if g_mu is None else g_mu
+        B.fwi_adjoint_gradient(self.plan, stream, rho, lam, mu, wavelet, residual, self.workspace,
+                               g_lam, g_mu)
+        return g_lam, g_mu
+
+    def apply_operator(self, which, rho, lam, mu, x0, x1, x2, out=None, stream=None):
+        out = torch.empty_like(x1) if out is None else out
+        B.fwi_apply_operator(self.plan, stream, which, rho, lam, mu, x0, x1, x2, self.workspace, out)
+        return out
