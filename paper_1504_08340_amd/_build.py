@@ -24,15 +24,16 @@ def hipcc():
     return exe
 
 
-def build(verbose=False) -> str:
-    """Compile csrc/pmlfwi.hip into libpmlfwi.so next to this file."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(HERE, "..", "include"), SRC, "-o", tmp]
+def build(verbose=False, out=LIB, defines=()) -> str:
+    """Compile csrc/pmlfwi.hip into libpmlfwi.so (next to this file by default)."""
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-I", os.path.join(HERE, "..", "include"),
+           SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -11,7 +11,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpmlfwi.so")
+LIB_PATH = os.environ.get("PMLFWI_LIB") or os.path.join(HERE, "libpmlfwi.so")
 
 FWI_FP64, FWI_FP32 = 0, 1
 

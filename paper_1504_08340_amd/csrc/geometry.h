@@ -32,7 +32,17 @@ struct Geo {
   double Lps, Lpb;       // PML thickness on the sides / at the bottom
   double alpha0, beta0;
   int m;
+  // device tables, [NX + NY + NZ] entries per quantity, axes x | y | z:
+  //   tab: alpha, beta (PML profile), total and interior 1D lumped-mass factors
+  //   fo : ordinal of an index among the upper faces of the tile lattice, or -1
+  const double* tab;
+  const int* fo;
 };
+
+// Per-axis offsets into the [NX + NY + NZ] tables.
+__host__ __device__ inline int ax_y(const Geo& g) { return g.NX; }
+__host__ __device__ inline int ax_z(const Geo& g) { return g.NX + g.NY; }
+__host__ __device__ inline int ax_n(const Geo& g) { return g.NX + g.NY + g.NZ; }
 
 __host__ __device__ inline bool is_dirichlet(const Geo& g, int i, int j, int k) {
   return i == 0 || i == g.NX - 1 || j == 0 || j == g.NY - 1 || k == 0;
@@ -142,6 +152,25 @@ __host__ __device__ inline PmlCoef pml_coef(const Geo& g, int i, int j, int k) {
   return c;
 }
 
+// Same coefficients from the per-axis tables (no division or power on device).
+__device__ __forceinline__ PmlCoef pml_coef_tab(const Geo& g, int i, int j, int k) {
+  const int nt = ax_n(g);
+  const double* A = g.tab;
+  const double* B = g.tab + nt;
+  const double ax = A[i], ay = A[ax_y(g) + j], az = A[ax_z(g) + k];
+  const double bx = B[i], by = B[ax_y(g) + j], bz = B[ax_z(g) + k];
+  PmlCoef c;
+  c.Le[0] = ay * az; c.Lp[0] = ay * bz + by * az; c.Lw[0] = by * bz;
+  c.Le[1] = ax * az; c.Lp[1] = ax * bz + bx * az; c.Lw[1] = bx * bz;
+  c.Le[2] = ax * ay; c.Lp[2] = ax * by + bx * ay; c.Lw[2] = bx * by;
+  c.a = ax * ay * az;
+  c.b = ax * ay * bz + ax * by * az + bx * ay * az;
+  c.c = ax * by * bz + bx * ay * bz + bx * by * az;
+  c.d = bx * by * bz;
+  c.nbeta = (bx > 0.0) + (by > 0.0) + (bz > 0.0);
+  return c;
+}
+
 // One-dimensional lumped-mass factors: sum of LGL weights of the bricks of
 // [elo, ehi) that contain node l (weights 1/3, 4/3, 1/3).
 __host__ __device__ inline double mass1d(int l, int elo, int ehi) {
@@ -162,6 +191,16 @@ __host__ __device__ inline void lumped_masses(const Geo& g, int i, int j, int k,
   const double v = 0.125 * g.h * g.h * g.h;
   const double tot = v * mass1d(i, 0, g.EX) * mass1d(j, 0, g.EY) * mass1d(k, 0, g.EZ);
   mrd = v * mass1d(i, g.ps, g.ps + g.ex) * mass1d(j, g.ps, g.ps + g.ey) * mass1d(k, g.pb, g.EZ);
+  mp = tot - mrd;
+}
+
+__device__ __forceinline__ void lumped_masses_tab(const Geo& g, int i, int j, int k, double& mrd, double& mp) {
+  const int nt = ax_n(g);
+  const double* T = g.tab + 2 * nt;
+  const double* D = g.tab + 3 * nt;
+  const double v = 0.125 * g.h * g.h * g.h;
+  const double tot = v * T[i] * T[ax_y(g) + j] * T[ax_z(g) + k];
+  mrd = v * D[i] * D[ax_y(g) + j] * D[ax_z(g) + k];
   mp = tot - mrd;
 }
 

@@ -12,7 +12,21 @@
 //   [x1 u_x, u_y, u_z | x2 u_x, u_y, u_z] on the full grid, then P part
 //   21 x n_pml [x0 u (3) | x0 S (6) | x1 S (6) | x2 S (6)] on the PML shell.
 //   Stress order (xx, yy, zz, yz, xz, xy).
-// Residual layout (per source): 3 x n_nodes u-rows, then 6 x n_pml S-rows.
+//
+// Element work is done per tile of bricks (a workgroup per tile, all sources
+// in turn).  Scatter without atomics: a node lies on the upper face (local
+// index 2*count) of at most one tile per axis, so the set c of axes on which
+// it is an upper-face node differs for every tile containing it.  A tile
+// stores its partial sum for a box node with a plain store into partial
+// array c; the nodal kernel adds the arrays c that can be non-zero for the
+// node.  Array 0 uses the register index spaces (full grid for u-rows, PML
+// shell for S-rows); arrays c != 0 use the full grid with the axes in c
+// compressed to the upper-face positions.  Entries nobody writes stay zero
+// from the initial clear.
+//
+// Tiles are handed to the XCDs in contiguous runs: workgroup b of a grid
+// whose size is a multiple of 8 runs on XCD b mod 8 and takes tile
+// (b mod 8) * (grid/8) + b / 8, so neighbouring tiles share an L2.
 #pragma once
 #include "geometry.h"
 
@@ -24,11 +38,11 @@ enum { P_X0U = 0, P_X0S = 3, P_X1S = 9, P_X2S = 15, P_NCOMP = 21, U_NCOMP = 6 };
 __host__ __device__ constexpr int vidx(int i, int k) { return i == k ? i : 6 - i - k; }
 
 // Derivative of 1D basis a at LGL point q: D[q][a] (nodes -1, 0, 1).
-__device__ __forceinline__ double dlgl(int q, int a) {
+__device__ __forceinline__ float dlgl(int q, int a) {
   // rows q = 0: (-3/2, 2, -1/2); q = 1: (-1/2, 0, 1/2); q = 2: (1/2, -2, 3/2)
-  const double r0 = a == 0 ? -1.5 : (a == 1 ? 2.0 : -0.5);
-  const double r1 = a == 0 ? -0.5 : (a == 1 ? 0.0 : 0.5);
-  const double r2 = a == 0 ? 0.5 : (a == 1 ? -2.0 : 1.5);
+  const float r0 = a == 0 ? -1.5f : (a == 1 ? 2.0f : -0.5f);
+  const float r1 = a == 0 ? -0.5f : (a == 1 ? 0.0f : 0.5f);
+  const float r2 = a == 0 ? 0.5f : (a == 1 ? -2.0f : 1.5f);
   return q == 0 ? r0 : (q == 1 ? r1 : r2);
 }
 __device__ __forceinline__ double wlgl(int a) { return a == 1 ? 4.0 / 3.0 : 1.0 / 3.0; }
@@ -37,12 +51,50 @@ struct Tile {  // bricks [x, x+cx) x [y, y+cy) x [z, z+cz)
   int x, y, z, c;  // c = cx | cy << 8 | cz << 16
 };
 
+struct Part {             // partial residual arrays of one source
+  long long off[8];       // element offset of array c (array 0 at 0)
+  long long size[8];      // nodes of array c (c != 0: compressed box)
+  int nx[8], ny[8];       // x / y extents of array c
+  long long per_src;      // elements per source
+};
+
+__device__ __forceinline__ int face_mask(const Geo& g, int i, int j, int k) {
+  return (g.fo[i] >= 0) | ((g.fo[ax_y(g) + j] >= 0) << 1) | ((g.fo[ax_z(g) + k] >= 0) << 2);
+}
+
+__device__ __forceinline__ size_t part_node(const Geo& g, const Part& P, int c, int i, int j, int k) {
+  const int ii = (c & 1) ? g.fo[i] : i;
+  const int jj = (c & 2) ? g.fo[ax_y(g) + j] : j;
+  const int kk = (c & 4) ? g.fo[ax_z(g) + k] : k;
+  return (size_t)ii + (size_t)P.nx[c] * ((size_t)jj + (size_t)P.ny[c] * kk);
+}
+
+// Offset of u-row d / S-row v of a node in partial array c (within one source).
+__device__ __forceinline__ size_t part_u(const Geo& g, const Part& P, int c, int i, int j, int k,
+                                         size_t node, int d) {
+  if (c == 0) return (size_t)d * g.n_nodes + node;
+  return (size_t)P.off[c] + (size_t)d * P.size[c] + part_node(g, P, c, i, j, k);
+}
+__device__ __forceinline__ size_t part_s(const Geo& g, const Part& P, int c, int i, int j, int k,
+                                         size_t p, int v) {
+  if (c == 0) return 3 * (size_t)g.n_nodes + (size_t)v * g.n_pml + p;
+  return (size_t)P.off[c] + (3 + (size_t)v) * P.size[c] + part_node(g, P, c, i, j, k);
+}
+
+__device__ __forceinline__ int xcd_tile() {
+  const int per = gridDim.x >> 3;
+  const int b = blockIdx.x;
+  return (b & 7) * per + (b >> 3);
+}
+
 // Per-dimension list of the bricks of a tile that contain local node l:
 // (brick offset, position of the node in that brick).  At most two.
 __device__ __forceinline__ int node_bricks(int l, int cnt, int* e, int* p) {
   if (l & 1) {
     e[0] = (l - 1) >> 1;
     p[0] = 1;
+    e[1] = e[0];
+    p[1] = 1;
     return 1;
   }
   int n = 0;
@@ -56,6 +108,10 @@ __device__ __forceinline__ int node_bricks(int l, int cnt, int* e, int* p) {
     p[n] = 0;
     ++n;
   }
+  if (n == 1) {
+    e[1] = e[0];
+    p[1] = p[0];
+  }
   return n;
 }
 
@@ -67,142 +123,176 @@ __device__ __forceinline__ void atomic_add(R* p, R v) {
 // ---------------------------------------------------------------------------
 // Interior bricks: r_u += K_RD u  (u = x1 displacement of the input register).
 // GRAD: also  g -= b_s * sum_e w|J| (div z div u_f, 2 eps(z):eps(u_f)) at the
-// LGL nodes, z = the displacement read here, u_f = stored forward stage field.
-template <typename R, int TX, int TY, int TZ, bool GRAD>
-__global__ void __launch_bounds__(128)
-interior_element_kernel(Geo g, const Tile* __restrict__ tiles, const R* __restrict__ Ybase,
-                        long long ystride, const R* __restrict__ lam, const R* __restrict__ mu,
-                        R* __restrict__ rbase, long long rstride, const R* __restrict__ fwd,
-                        long long fstride, double gw, double* __restrict__ g_lam,
-                        double* __restrict__ g_mu) {
+// LGL nodes, z = the displacement read here, u_f = stored forward stage field,
+// summed over sources and added to FP64 accumulators (gacc: [8][2][n_nodes],
+// slot c indexed like the partial arrays).
+template <typename R, int TX, int TY, int TZ, bool GRAD, bool SRCLOOP>
+__global__ void __launch_bounds__(256)
+interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
+                        const R* __restrict__ Ybase, long long ystride, const R* __restrict__ lam,
+                        const R* __restrict__ mu, R* __restrict__ rbase, Part PT,
+                        const R* __restrict__ fwd, long long fstride, double gw,
+                        double* __restrict__ gacc, Part PG) {
   constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
   constexpr int NB = BX * BY * BZ, NP = 27 * TX * TY * TZ;
   __shared__ R sU[3][NB];
   __shared__ R sLam[NB], sMu[NB];
   __shared__ R sS[6][NP];
   __shared__ R sV[GRAD ? 3 : 1][GRAD ? NB : 1];
-  __shared__ double sG[GRAD ? 2 : 1][GRAD ? NP : 1];
+  __shared__ R sG[GRAD ? 2 : 1][GRAD ? NP : 1];
+  __shared__ double sGacc[GRAD ? 2 : 1][GRAD ? NB : 1];   // summed over sources
 
-  const Tile t = tiles[blockIdx.x];
-  const int src = blockIdx.y;
+  const int ti = xcd_tile();
+  if (ti >= ntiles) return;
+  const Tile t = tiles[ti];
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
   const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
   const size_t nn = (size_t)g.n_nodes;
-  const R* Yu = Ybase + (size_t)src * ystride;
-  R* res = rbase + (size_t)src * rstride;
-  const R* F = GRAD ? fwd + (size_t)src * fstride : nullptr;
+  const R s2h = R(2.0 / g.h);
 
   for (int n = threadIdx.x; n < NB; n += blockDim.x) {
     const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
     if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-    const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-    const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
-    const int mi = interior_index(g, i, j, k);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) sU[d][n] = Yu[d * nn + node];
+    const int mi = interior_index(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz);
     sLam[n] = lam[mi];
     sMu[n] = mu[mi];
     if constexpr (GRAD) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) sV[d][n] = F[(size_t)d * g.n_int + mi];
+      sGacc[0][n] = 0.0;
+      sGacc[1][n] = 0.0;
     }
   }
-  __syncthreads();
 
-  const R s2h = R(2.0 / g.h);
-  for (int q = threadIdx.x; q < NP; q += blockDim.x) {
-    const int pt = q % 27, e = q / 27;
-    const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
-    if (ea >= cx || eb >= cy || ec >= cz) continue;
-    const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
-    const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
-    const int nq = lx + BX * (ly + BY * lz);
-    R G[3][3], Gf[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      R gx = 0, gy = 0, gz = 0, fx = 0, fy = 0, fz = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const R cxa = R(dlgl(qa, a)), cya = R(dlgl(qb, a)), cza = R(dlgl(qc, a));
-        const int nx = (2 * ea + a) + BX * (ly + BY * lz);
-        const int ny = lx + BX * ((2 * eb + a) + BY * lz);
-        const int nz = lx + BX * (ly + BY * (2 * ec + a));
-        gx += cxa * sU[d][nx];
-        gy += cya * sU[d][ny];
-        gz += cza * sU[d][nz];
-        if constexpr (GRAD) {
-          fx += cxa * sV[d][nx];
-          fy += cya * sV[d][ny];
-          fz += cza * sV[d][nz];
-        }
-      }
-      G[d][0] = gx * s2h; G[d][1] = gy * s2h; G[d][2] = gz * s2h;
-      if constexpr (GRAD) { Gf[d][0] = fx * s2h; Gf[d][1] = fy * s2h; Gf[d][2] = fz * s2h; }
-    }
-    const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
-    const R la = sLam[nq], m = sMu[nq];
-    const R tr = G[0][0] + G[1][1] + G[2][2];
-    sS[0][q] = wq * (la * tr + 2 * m * G[0][0]);
-    sS[1][q] = wq * (la * tr + 2 * m * G[1][1]);
-    sS[2][q] = wq * (la * tr + 2 * m * G[2][2]);
-    sS[3][q] = wq * (m * (G[1][2] + G[2][1]));
-    sS[4][q] = wq * (m * (G[0][2] + G[2][0]));
-    sS[5][q] = wq * (m * (G[0][1] + G[1][0]));
-    if constexpr (GRAD) {
-      const double dz = (double)tr, du = (double)(Gf[0][0] + Gf[1][1] + Gf[2][2]);
-      double ee = 2.0 * ((double)G[0][0] * Gf[0][0] + (double)G[1][1] * Gf[1][1] +
-                         (double)G[2][2] * Gf[2][2]);
-      ee += (double)(G[1][2] + G[2][1]) * (double)(Gf[1][2] + Gf[2][1]);
-      ee += (double)(G[0][2] + G[2][0]) * (double)(Gf[0][2] + Gf[2][0]);
-      ee += (double)(G[0][1] + G[1][0]) * (double)(Gf[0][1] + Gf[1][0]);
-      sG[0][q] = (double)wq * dz * du;
-      sG[1][q] = (double)wq * ee;
-    }
-  }
-  __syncthreads();
-
-  for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-    const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-    if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-    const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-    int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
-    const int nex = node_bricks(lx, cx, exs, pxs);
-    const int ney = node_bricks(ly, cy, eys, pys);
-    const int nez = node_bricks(lz, cz, ezs, pzs);
-    R r0 = 0, r1 = 0, r2 = 0;
-    double gl = 0.0, gm = 0.0;
-    for (int a3 = 0; a3 < nez; ++a3)
-      for (int a2 = 0; a2 < ney; ++a2)
-        for (int a1 = 0; a1 < nex; ++a1) {
-          const int ea = exs[a1], eb = eys[a2], ec = ezs[a3];
-          const int pa = pxs[a1], pb = pys[a2], pc = pzs[a3];
-          const int eb0 = 27 * (ea + TX * (eb + TY * ec));
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const R cxa = R(dlgl(a, pa)), cya = R(dlgl(a, pb)), cza = R(dlgl(a, pc));
-            const int qx = eb0 + a + 3 * pb + 9 * pc;
-            const int qy = eb0 + pa + 3 * a + 9 * pc;
-            const int qz = eb0 + pa + 3 * pb + 9 * a;
-            r0 += cxa * sS[0][qx] + cya * sS[5][qy] + cza * sS[4][qz];
-            r1 += cxa * sS[5][qx] + cya * sS[1][qy] + cza * sS[3][qz];
-            r2 += cxa * sS[4][qx] + cya * sS[3][qy] + cza * sS[2][qz];
-          }
-          if constexpr (GRAD) {
-            const int qn = eb0 + pa + 3 * pb + 9 * pc;
-            gl += sG[0][qn];
-            gm += sG[1][qn];
-          }
-        }
-    if (!is_dirichlet(g, i, j, k)) {
+  static_assert(SRCLOOP || !GRAD, "gradient sums over sources inside the workgroup");
+  const int src0 = SRCLOOP ? 0 : (int)blockIdx.y, src1 = SRCLOOP ? nsrc : src0 + 1;
+  for (int src = src0; src < src1; ++src) {
+    const R* Yu = Ybase + (size_t)src * ystride;
+    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
+      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
+      const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
       const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
-      atomic_add(&res[node], r0 * s2h);
-      atomic_add(&res[nn + node], r1 * s2h);
-      atomic_add(&res[2 * nn + node], r2 * s2h);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sU[d][n] = Yu[d * nn + node];
+      if constexpr (GRAD) {
+        const R* F = fwd + (size_t)src * fstride;
+        const int mi = interior_index(g, i, j, k);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sV[d][n] = F[(size_t)d * g.n_int + mi];
+      }
     }
-    if constexpr (GRAD) {
-      const int mi = interior_index(g, i, j, k);
-      atomic_add(&g_lam[mi], gw * gl);
-      atomic_add(&g_mu[mi], gw * gm);
+    __syncthreads();
+
+    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+      const int pt = q % 27, e = q / 27;
+      const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
+      if (ea >= cx || eb >= cy || ec >= cz) continue;
+      const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
+      const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
+      const int nq = lx + BX * (ly + BY * lz);
+      R G[3][3], Gf[3][3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        R gx = 0, gy = 0, gz = 0, fx = 0, fy = 0, fz = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const R cxa = R(dlgl(qa, a)), cya = R(dlgl(qb, a)), cza = R(dlgl(qc, a));
+          const int nx = (2 * ea + a) + BX * (ly + BY * lz);
+          const int ny = lx + BX * ((2 * eb + a) + BY * lz);
+          const int nz = lx + BX * (ly + BY * (2 * ec + a));
+          gx += cxa * sU[d][nx];
+          gy += cya * sU[d][ny];
+          gz += cza * sU[d][nz];
+          if constexpr (GRAD) {
+            fx += cxa * sV[d][nx];
+            fy += cya * sV[d][ny];
+            fz += cza * sV[d][nz];
+          }
+        }
+        G[d][0] = gx * s2h; G[d][1] = gy * s2h; G[d][2] = gz * s2h;
+        if constexpr (GRAD) { Gf[d][0] = fx * s2h; Gf[d][1] = fy * s2h; Gf[d][2] = fz * s2h; }
+      }
+      const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
+      const R la = sLam[nq], m = sMu[nq];
+      const R tr = G[0][0] + G[1][1] + G[2][2];
+      sS[0][q] = wq * (la * tr + 2 * m * G[0][0]);
+      sS[1][q] = wq * (la * tr + 2 * m * G[1][1]);
+      sS[2][q] = wq * (la * tr + 2 * m * G[2][2]);
+      sS[3][q] = wq * (m * (G[1][2] + G[2][1]));
+      sS[4][q] = wq * (m * (G[0][2] + G[2][0]));
+      sS[5][q] = wq * (m * (G[0][1] + G[1][0]));
+      if constexpr (GRAD) {
+        // per-stage products in the state precision; summed in FP64 below
+        const R du = Gf[0][0] + Gf[1][1] + Gf[2][2];
+        R ee = 2 * (G[0][0] * Gf[0][0] + G[1][1] * Gf[1][1] + G[2][2] * Gf[2][2]);
+        ee += (G[1][2] + G[2][1]) * (Gf[1][2] + Gf[2][1]);
+        ee += (G[0][2] + G[2][0]) * (Gf[0][2] + Gf[2][0]);
+        ee += (G[0][1] + G[1][0]) * (Gf[0][1] + Gf[1][0]);
+        sG[0][q] = wq * tr * du;
+        sG[1][q] = wq * ee;
+      }
+    }
+    __syncthreads();
+
+    R* res = rbase + (size_t)src * PT.per_src;
+    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
+      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
+      const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
+      int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
+      const int nex = node_bricks(lx, cx, exs, pxs);
+      const int ney = node_bricks(ly, cy, eys, pys);
+      const int nez = node_bricks(lz, cz, ezs, pzs);
+      R r0 = 0, r1 = 0, r2 = 0;
+      R gl = 0, gm = 0;
+#pragma unroll
+      for (int a3 = 0; a3 < 2; ++a3)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int a1 = 0; a1 < 2; ++a1) {
+            if (a1 >= nex || a2 >= ney || a3 >= nez) continue;
+            const int ea = exs[a1], eb = eys[a2], ec = ezs[a3];
+            const int pa = pxs[a1], pb = pys[a2], pc = pzs[a3];
+            const int eb0 = 27 * (ea + TX * (eb + TY * ec));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              const R cxa = R(dlgl(a, pa)), cya = R(dlgl(a, pb)), cza = R(dlgl(a, pc));
+              const int qx = eb0 + a + 3 * pb + 9 * pc;
+              const int qy = eb0 + pa + 3 * a + 9 * pc;
+              const int qz = eb0 + pa + 3 * pb + 9 * a;
+              r0 += cxa * sS[0][qx] + cya * sS[5][qy] + cza * sS[4][qz];
+              r1 += cxa * sS[5][qx] + cya * sS[1][qy] + cza * sS[3][qz];
+              r2 += cxa * sS[4][qx] + cya * sS[3][qy] + cza * sS[2][qz];
+            }
+            if constexpr (GRAD) {
+              const int qn = eb0 + pa + 3 * pb + 9 * pc;
+              gl += sG[0][qn];
+              gm += sG[1][qn];
+            }
+          }
+      const int c = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+      if (!is_dirichlet(g, i, j, k)) {
+        const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
+        res[part_u(g, PT, c, i, j, k, node, 0)] = r0 * s2h;
+        res[part_u(g, PT, c, i, j, k, node, 1)] = r1 * s2h;
+        res[part_u(g, PT, c, i, j, k, node, 2)] = r2 * s2h;
+      }
+      if constexpr (GRAD) {
+        sGacc[0][n] += (double)gl;
+        sGacc[1][n] += (double)gm;
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (GRAD) {
+    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
+      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
+      const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
+      const int c = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+      const size_t o = (size_t)PG.off[c] + part_node(g, PG, c, i, j, k);
+      gacc[o] += gw * sGacc[0][n];
+      gacc[o + PG.size[c]] += gw * sGacc[1][n];
     }
   }
 }
@@ -217,183 +307,207 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, const R* __restri
 //   u-rows:  r_u += int grad w~ : T',  T'_ik = -(mu (1+d_ik) Z_k,ik + lam d_ik tr Z_i),
 //            Z_k = Le_kk T2 + Lp_kk T1 + Lw_kk T0 (symmetric stress-like fields)
 //   S-rows:  r_S += int T~_ab (H_ab + H_ba)  (a != b),  H_aa  (a = b).
-template <typename R, int TX, int TY, int TZ, bool ADJ>
-__global__ void __launch_bounds__(128)
-pml_element_kernel(Geo g, const Tile* __restrict__ tiles, const R* __restrict__ Ybase,
-                   long long ystride, const R* __restrict__ lam, const R* __restrict__ mu,
-                   R* __restrict__ rbase, long long rstride) {
+template <typename R, int TX, int TY, int TZ, bool ADJ, bool SRCLOOP>
+__global__ void __launch_bounds__(256)
+pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
+                   const R* __restrict__ Ybase, long long ystride, const R* __restrict__ lam,
+                   const R* __restrict__ mu, R* __restrict__ rbase, Part PT) {
   constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
   constexpr int NB = BX * BY * BZ, NP = 27 * TX * TY * TZ;
   __shared__ R sW[9][NB];   // [3k + i]: Le_kk u'_i + Lp_kk u_i + Lw_kk ubar_i
   __shared__ R sT[9][NB];   // [3i + k]: nodal stress-like tensor of the u-rows
-  __shared__ R sLam[ADJ ? 1 : NB], sMu[ADJ ? 1 : NB];
+  __shared__ R sLam[NB], sMu[NB];
   __shared__ R sQ[6][NP];
 
-  const Tile t = tiles[blockIdx.x];
-  const int src = blockIdx.y;
+  const int ti = xcd_tile();
+  if (ti >= ntiles) return;
+  const Tile t = tiles[ti];
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
   const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
   const size_t nn = (size_t)g.n_nodes, np = (size_t)g.n_pml;
-  const R* Y = Ybase + (size_t)src * ystride;
-  const R* P = Y + 6 * nn;
-  R* res = rbase + (size_t)src * rstride;
-
-  for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-    const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-    if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-    const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-    const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
-    const size_t p = (size_t)pml_index(g, i, j, k);
-    const PmlCoef c = pml_coef(g, i, j, k);
-    const bool hist = c.nbeta >= 2;
-    R u1[3], u2[3], u0[3], s0[6], s1[6], s2[6];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      u1[d] = Y[d * nn + node];
-      u2[d] = Y[(3 + d) * nn + node];
-      u0[d] = hist ? P[(P_X0U + d) * np + p] : R(0);
-    }
-#pragma unroll
-    for (int v = 0; v < 6; ++v) {
-      s1[v] = P[(P_X1S + v) * np + p];
-      s2[v] = P[(P_X2S + v) * np + p];
-      s0[v] = hist ? P[(P_X0S + v) * np + p] : R(0);
-    }
-    R Le[3], Lp[3], Lw[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { Le[d] = R(c.Le[d]); Lp[d] = R(c.Lp[d]); Lw[d] = R(c.Lw[d]); }
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) sW[3 * kk + ii][n] = Le[kk] * u2[ii] + Lp[kk] * u1[ii] + Lw[kk] * u0[ii];
-    const int mi = material_index(g, i, j, k);
-    const R la = lam[mi], m = mu[mi];
-    if constexpr (!ADJ) {
-      sLam[n] = la;
-      sMu[n] = m;
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          const int v = vidx(ii, kk);
-          sT[3 * ii + kk][n] = Le[kk] * s2[v] + Lp[kk] * s1[v] + Lw[kk] * s0[v];
-        }
-    } else {
-      const R t2 = s2[0] + s2[1] + s2[2], t1 = s1[0] + s1[1] + s1[2], t0 = s0[0] + s0[1] + s0[2];
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          const int v = vidx(ii, kk);
-          const R z = Le[kk] * s2[v] + Lp[kk] * s1[v] + Lw[kk] * s0[v];
-          R val = (ii == kk ? R(2) : R(1)) * m * z;
-          if (ii == kk) val += la * (Le[ii] * t2 + Lp[ii] * t1 + Lw[ii] * t0);
-          sT[3 * ii + kk][n] = -val;
-        }
-    }
-  }
-  __syncthreads();
-
   const R s2h = R(2.0 / g.h);
-  for (int q = threadIdx.x; q < NP; q += blockDim.x) {
-    const int pt = q % 27, e = q / 27;
-    const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
-    if (ea >= cx || eb >= cy || ec >= cz) continue;
-    const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
-    const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
-    R H[3][3];
-#pragma unroll
-    for (int ii = 0; ii < 3; ++ii) {
-      R hx = 0, hy = 0, hz = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        hx += R(dlgl(qa, a)) * sW[0 + ii][(2 * ea + a) + BX * (ly + BY * lz)];
-        hy += R(dlgl(qb, a)) * sW[3 + ii][lx + BX * ((2 * eb + a) + BY * lz)];
-        hz += R(dlgl(qc, a)) * sW[6 + ii][lx + BX * (ly + BY * (2 * ec + a))];
-      }
-      H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
-    }
-    const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
-    if constexpr (!ADJ) {
-      const int nq = lx + BX * (ly + BY * lz);
-      const R la = sLam[nq], m = sMu[nq];
-      const R tr = H[0][0] + H[1][1] + H[2][2];
-      sQ[0][q] = -wq * (la * tr + 2 * m * H[0][0]);
-      sQ[1][q] = -wq * (la * tr + 2 * m * H[1][1]);
-      sQ[2][q] = -wq * (la * tr + 2 * m * H[2][2]);
-      sQ[3][q] = -wq * (m * (H[1][2] + H[2][1]));
-      sQ[4][q] = -wq * (m * (H[0][2] + H[2][0]));
-      sQ[5][q] = -wq * (m * (H[0][1] + H[1][0]));
-    } else {
-      sQ[0][q] = wq * H[0][0];
-      sQ[1][q] = wq * H[1][1];
-      sQ[2][q] = wq * H[2][2];
-      sQ[3][q] = wq * (H[1][2] + H[2][1]);
-      sQ[4][q] = wq * (H[0][2] + H[2][0]);
-      sQ[5][q] = wq * (H[0][1] + H[1][0]);
-    }
-  }
-  __syncthreads();
-
   const R vol = R(0.125 * g.h * g.h * g.h);
+
   for (int n = threadIdx.x; n < NB; n += blockDim.x) {
     const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
     if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-    const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-    int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
-    const int nex = node_bricks(lx, cx, exs, pxs);
-    const int ney = node_bricks(ly, cy, eys, pys);
-    const int nez = node_bricks(lz, cz, ezs, pzs);
-    // 1D weight sums of the tile's bricks that contain the node
-    R Sx = 0, Sy = 0, Sz = 0;
-    for (int a = 0; a < nex; ++a) Sx += R(wlgl(pxs[a]));
-    for (int a = 0; a < ney; ++a) Sy += R(wlgl(pys[a]));
-    for (int a = 0; a < nez; ++a) Sz += R(wlgl(pzs[a]));
-    // u-rows: the stress-like tensor is nodal, so each direction factorizes
-    R dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0}, dz[3] = {0, 0, 0};
-    for (int b = 0; b < nex; ++b)
+    const int mi = material_index(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz);
+    sLam[n] = lam[mi];
+    sMu[n] = mu[mi];
+  }
+  __syncthreads();
+
+  const int src0 = SRCLOOP ? 0 : (int)blockIdx.y, src1 = SRCLOOP ? nsrc : src0 + 1;
+  for (int src = src0; src < src1; ++src) {
+    const R* Y = Ybase + (size_t)src * ystride;
+    const R* P = Y + 6 * nn;
+    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
+      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
+      const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
+      const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
+      const size_t gp = (size_t)pml_index(g, gi, gj, gk);
+      const PmlCoef c = pml_coef_tab(g, gi, gj, gk);
+      const bool hist = c.nbeta >= 2;
+      R Le[3], Lp[3], Lw[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const R cf = R(dlgl(a, pxs[b]) * wlgl(a));
-        const int nx = (2 * exs[b] + a) + BX * (ly + BY * lz);
+      for (int d = 0; d < 3; ++d) { Le[d] = R(c.Le[d]); Lp[d] = R(c.Lp[d]); Lw[d] = R(c.Lw[d]); }
+      R u1[3], u2[3], u0[3], s0[6], s1[6], s2[6];
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) dx[ii] += cf * sT[3 * ii + 0][nx];
+      for (int d = 0; d < 3; ++d) {
+        u1[d] = Y[d * nn + gnode];
+        u2[d] = Y[(3 + d) * nn + gnode];
+        u0[d] = hist ? P[(P_X0U + d) * np + gp] : R(0);
       }
-    for (int b = 0; b < ney; ++b)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const R cf = R(dlgl(a, pys[b]) * wlgl(a));
-        const int ny = lx + BX * ((2 * eys[b] + a) + BY * lz);
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) dy[ii] += cf * sT[3 * ii + 1][ny];
+      for (int v = 0; v < 6; ++v) {
+        s1[v] = P[(P_X1S + v) * np + gp];
+        s2[v] = P[(P_X2S + v) * np + gp];
+        s0[v] = hist ? P[(P_X0S + v) * np + gp] : R(0);
       }
-    for (int b = 0; b < nez; ++b)
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const R cf = R(dlgl(a, pzs[b]) * wlgl(a));
-        const int nz = lx + BX * (ly + BY * (2 * ezs[b] + a));
+      for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii) dz[ii] += cf * sT[3 * ii + 2][nz];
+        for (int ii = 0; ii < 3; ++ii) sW[3 * kk + ii][n] = Le[kk] * u2[ii] + Lp[kk] * u1[ii] + Lw[kk] * u0[ii];
+      if constexpr (!ADJ) {
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) {
+            const int v = vidx(ii, kk);
+            sT[3 * ii + kk][n] = Le[kk] * s2[v] + Lp[kk] * s1[v] + Lw[kk] * s0[v];
+          }
+      } else {
+        const R la = sLam[n], m = sMu[n];
+        const R t2 = s2[0] + s2[1] + s2[2], t1 = s1[0] + s1[1] + s1[2], t0 = s0[0] + s0[1] + s0[2];
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk) {
+            const int v = vidx(ii, kk);
+            const R z = Le[kk] * s2[v] + Lp[kk] * s1[v] + Lw[kk] * s0[v];
+            R val = (ii == kk ? R(2) : R(1)) * m * z;
+            if (ii == kk) val += la * (Le[ii] * t2 + Lp[ii] * t1 + Lw[ii] * t0);
+            sT[3 * ii + kk][n] = -val;
+          }
       }
-    // S-rows: sum of the point values of every tile brick containing the node
-    R q6[6] = {0, 0, 0, 0, 0, 0};
-    for (int a3 = 0; a3 < nez; ++a3)
-      for (int a2 = 0; a2 < ney; ++a2)
-        for (int a1 = 0; a1 < nex; ++a1) {
-          const int qn = 27 * (exs[a1] + TX * (eys[a2] + TY * ezs[a3])) + pxs[a1] + 3 * pys[a2] + 9 * pzs[a3];
-#pragma unroll
-          for (int v = 0; v < 6; ++v) q6[v] += sQ[v][qn];
-        }
-    const size_t p = (size_t)pml_index(g, i, j, k);
-#pragma unroll
-    for (int v = 0; v < 6; ++v) atomic_add(&res[3 * nn + v * np + p], q6[v]);
-    if (!is_dirichlet(g, i, j, k)) {
-      const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
-      const R f = vol * s2h;
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii)
-        atomic_add(&res[ii * nn + node], f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]));
     }
+    __syncthreads();
+
+    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+      const int pt = q % 27, e = q / 27;
+      const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
+      if (ea >= cx || eb >= cy || ec >= cz) continue;
+      const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
+      const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
+      R H[3][3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        R hx = 0, hy = 0, hz = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          hx += R(dlgl(qa, a)) * sW[0 + ii][(2 * ea + a) + BX * (ly + BY * lz)];
+          hy += R(dlgl(qb, a)) * sW[3 + ii][lx + BX * ((2 * eb + a) + BY * lz)];
+          hz += R(dlgl(qc, a)) * sW[6 + ii][lx + BX * (ly + BY * (2 * ec + a))];
+        }
+        H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
+      }
+      const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
+      if constexpr (!ADJ) {
+        const int nq = lx + BX * (ly + BY * lz);
+        const R la = sLam[nq], m = sMu[nq];
+        const R tr = H[0][0] + H[1][1] + H[2][2];
+        sQ[0][q] = -wq * (la * tr + 2 * m * H[0][0]);
+        sQ[1][q] = -wq * (la * tr + 2 * m * H[1][1]);
+        sQ[2][q] = -wq * (la * tr + 2 * m * H[2][2]);
+        sQ[3][q] = -wq * (m * (H[1][2] + H[2][1]));
+        sQ[4][q] = -wq * (m * (H[0][2] + H[2][0]));
+        sQ[5][q] = -wq * (m * (H[0][1] + H[1][0]));
+      } else {
+        sQ[0][q] = wq * H[0][0];
+        sQ[1][q] = wq * H[1][1];
+        sQ[2][q] = wq * H[2][2];
+        sQ[3][q] = wq * (H[1][2] + H[2][1]);
+        sQ[4][q] = wq * (H[0][2] + H[2][0]);
+        sQ[5][q] = wq * (H[0][1] + H[1][0]);
+      }
+    }
+    __syncthreads();
+
+    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
+      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
+      const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
+      const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
+      const size_t gp = (size_t)pml_index(g, gi, gj, gk);
+      int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
+      const int nex = node_bricks(lx, cx, exs, pxs);
+      const int ney = node_bricks(ly, cy, eys, pys);
+      const int nez = node_bricks(lz, cz, ezs, pzs);
+      // 1D weight sums of the tile's bricks that contain the node
+      const R Sx = R(wlgl(pxs[0]) + (nex > 1 ? wlgl(pxs[1]) : 0.0));
+      const R Sy = R(wlgl(pys[0]) + (ney > 1 ? wlgl(pys[1]) : 0.0));
+      const R Sz = R(wlgl(pzs[0]) + (nez > 1 ? wlgl(pzs[1]) : 0.0));
+      // u-rows: the stress-like tensor is nodal, so each direction factorizes
+      R dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0}, dz[3] = {0, 0, 0};
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b >= nex) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const R cf = R(dlgl(a, pxs[b]) * wlgl(a));
+          const int nx = (2 * exs[b] + a) + BX * (ly + BY * lz);
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) dx[ii] += cf * sT[3 * ii + 0][nx];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b >= ney) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const R cf = R(dlgl(a, pys[b]) * wlgl(a));
+          const int ny = lx + BX * ((2 * eys[b] + a) + BY * lz);
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) dy[ii] += cf * sT[3 * ii + 1][ny];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b >= nez) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const R cf = R(dlgl(a, pzs[b]) * wlgl(a));
+          const int nz = lx + BX * (ly + BY * (2 * ezs[b] + a));
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) dz[ii] += cf * sT[3 * ii + 2][nz];
+        }
+      }
+      // S-rows: sum of the point values of every tile brick containing the node
+      R q6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int a3 = 0; a3 < 2; ++a3)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int a1 = 0; a1 < 2; ++a1) {
+            if (a1 >= nex || a2 >= ney || a3 >= nez) continue;
+            const int qn = 27 * (exs[a1] + TX * (eys[a2] + TY * ezs[a3])) + pxs[a1] + 3 * pys[a2] + 9 * pzs[a3];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) q6[v] += sQ[v][qn];
+          }
+      R* res = rbase + (size_t)src * PT.per_src;
+      const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) res[part_s(g, PT, cs, gi, gj, gk, gp, v)] = q6[v];
+      if (!is_dirichlet(g, gi, gj, gk)) {
+        const R f = vol * s2h;
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii)
+          res[part_u(g, PT, cs, gi, gj, gk, gnode, ii)] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -403,17 +517,18 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, const R* __restrict__ 
 //   mode 0:  acc = Xn + cA K,  Yout = Xn + cY K
 //   mode 1:  acc += cA K,      Yout = Xn + cY K
 //   mode 2:  Xn = acc + cA K
-// The residual is cleared for the next stage.  Threads [0, n_nodes) handle
-// the displacement rows, [n_nodes, n_nodes + n_pml) the PML rows.
+// Threads [0, n_nodes) handle the displacement rows, [n_nodes, n_nodes +
+// n_pml) the PML rows.
 template <typename R>
 struct NodalArgs {
   const R* Yin;
   R* Yout;
   R* Xn;
   R* acc;
-  R* res;
+  const R* res;               // partial arrays of source 0
+  Part part;
   const R* invMu;
-  long long reg, rstr;
+  long long reg;
   R cA, cY;
   int mode;
   const int* src_node;        // nullptr: no load
@@ -424,6 +539,36 @@ struct NodalArgs {
   long long store_stride;     // interior closure (per source stride), or nullptr
 };
 
+// Where a node's contributions sit in the partial arrays: array 0 always, and
+// array c != 0 when every axis of c is an upper-face axis of the node.
+struct PartSlots {
+  int mask;
+  size_t nc[8];   // node index inside array c (c != 0: compressed box)
+};
+
+__device__ __forceinline__ PartSlots part_slots(const Geo& g, const Part& P, int i, int j, int k) {
+  PartSlots S;
+  const int fx = g.fo[i], fy = g.fo[ax_y(g) + j], fz = g.fo[ax_z(g) + k];
+  S.mask = (fx >= 0) | ((fy >= 0) << 1) | ((fz >= 0) << 2);
+#pragma unroll
+  for (int c = 1; c < 8; ++c) {
+    const int ii = (c & 1) ? fx : i, jj = (c & 2) ? fy : j, kk = (c & 4) ? fz : k;
+    S.nc[c] = (size_t)ii + (size_t)P.nx[c] * ((size_t)jj + (size_t)P.ny[c] * kk);
+  }
+  return S;
+}
+
+// Sum over the partial arrays of row `row` (0..2 u-rows, 3..8 S-rows); off0 is
+// the entry in array 0.
+template <typename R>
+__device__ __forceinline__ R gather_rows(const Part& P, const PartSlots& S, const R* res, size_t off0, int row) {
+  R s = res[off0];
+#pragma unroll
+  for (int c = 1; c < 8; ++c)
+    if ((S.mask & c) == c) s += res[(size_t)P.off[c] + (size_t)row * P.size[c] + S.nc[c]];
+  return s;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
@@ -433,7 +578,7 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   R* Yo = A.Yout ? A.Yout + (size_t)src * A.reg : nullptr;
   R* X = A.Xn + (size_t)src * A.reg;
   R* C = A.acc + (size_t)src * A.reg;
-  R* res = A.res + (size_t)src * A.rstr;
+  const R* res = A.res + (size_t)src * A.part.per_src;
   const R cA = A.cA, cY = A.cY;
   const int mode = A.mode;
 
@@ -443,13 +588,13 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     const int r_ = node - k * g.plane;
     const int j = r_ / g.NX, i = r_ - j * g.NX;
     if (is_dirichlet(g, i, j, k)) return;
+    const PartSlots PS = part_slots(g, A.part, i, j, k);
     R u1[3], u2[3], rr[3], a2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       u1[d] = Y[d * nn + node];
       u2[d] = Y[(3 + d) * nn + node];
-      rr[d] = res[d * nn + node];
-      res[d * nn + node] = R(0);
+      rr[d] = gather_rows(A.part, PS, res, (size_t)d * nn + node, d);
     }
     R f[3] = {0, 0, 0};
     if (A.src_node && A.src_node[src] == node) {
@@ -462,8 +607,8 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     for (int d = 0; d < 3; ++d) a2[d] = im * (f[d] - rr[d]);
     if (in_pml(g, i, j, k)) {
       double mrd, mp;
-      lumped_masses(g, i, j, k, mrd, mp);
-      const PmlCoef c = pml_coef(g, i, j, k);
+      lumped_masses_tab(g, i, j, k, mrd, mp);
+      const PmlCoef c = pml_coef_tab(g, i, j, k);
       const R kap = R(mp / (mrd + c.a * mp));
       R u0[3] = {0, 0, 0};
       if (c.nbeta >= 2) {
@@ -511,15 +656,15 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const size_t p = (size_t)pp;
   int i, j, k;
   pml_coords(g, (int)p, i, j, k);
-  const PmlCoef c = pml_coef(g, i, j, k);
+  const PmlCoef c = pml_coef_tab(g, i, j, k);
   double mrd, mp;
-  lumped_masses(g, i, j, k, mrd, mp);
+  lumped_masses_tab(g, i, j, k, mrd, mp);
   const bool hist = c.nbeta >= 2;
   const R* PY = Y + 6 * nn;
   R* PX = X + 6 * nn;
   R* PC = C + 6 * nn;
   R* PO = Yo ? Yo + 6 * nn : nullptr;
-  R* rS = res + 3 * nn;
+  const PartSlots PS = part_slots(g, A.part, i, j, k);
   const R ia = R(1.0 / c.a), iam = R(1.0 / (c.a * mp));
   const R cb = R(c.b), cc = R(c.c), cd = R(c.d);
 
@@ -538,8 +683,7 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   for (int v = 0; v < 6; ++v) {
     const R s1 = PY[(P_X1S + v) * np + p], s2 = PY[(P_X2S + v) * np + p];
     const R s0 = hist ? PY[(P_X0S + v) * np + p] : R(0);
-    const R rv = rS[v * np + p];
-    rS[v * np + p] = R(0);
+    const R rv = gather_rows(A.part, PS, res, 3 * nn + (size_t)v * np + p, 3 + v);
     const R a2 = -rv * iam - ia * (cb * s2 + cc * s1 + cd * s0);
     if (hist) upd(P_X0S + v, s1);
     upd(P_X1S + v, s2);
@@ -564,8 +708,8 @@ __global__ void inv_mass_kernel(Geo g, const double* __restrict__ rho, R* __rest
     return;
   }
   double mrd, mp;
-  lumped_masses(g, i, j, k, mrd, mp);
-  const PmlCoef c = pml_coef(g, i, j, k);
+  lumped_masses_tab(g, i, j, k, mrd, mp);
+  const PmlCoef c = pml_coef_tab(g, i, j, k);
   invMu[node] = R(1.0 / (rho[material_index(g, i, j, k)] * (mrd + c.a * mp)));
 }
 

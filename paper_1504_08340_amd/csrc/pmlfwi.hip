@@ -24,6 +24,11 @@ struct fwi_plan {
   int32_t* d_src = nullptr;
   double* d_dir = nullptr;
   int32_t* d_rec = nullptr;
+  std::vector<double> tab;           // per-axis PML profile and 1D mass factors
+  std::vector<int> fo;               // per-axis upper-face ordinals of the tile lattice
+  int nface[3] = {0, 0, 0};
+  double* d_tab = nullptr;
+  int* d_fo = nullptr;
   const void* fwd_ws = nullptr;   // workspace holding the last forward's data
   std::string err;
   // sampled kernel timing
@@ -62,7 +67,19 @@ struct TimedLaunch {
 
 namespace {
 
-constexpr int TX = 2, TY = 2, TZ = 2;   // bricks per element tile
+// Element tiles (bricks per axis) and whether a workgroup walks all sources of
+// its tile (true) or one source per workgroup (false).
+#ifndef PMLFWI_TX
+#define PMLFWI_TX 4
+#define PMLFWI_TY 2
+#define PMLFWI_TZ 2
+#endif
+#ifndef PMLFWI_SRCLOOP
+#define PMLFWI_SRCLOOP false
+#endif
+constexpr int TX = PMLFWI_TX, TY = PMLFWI_TY, TZ = PMLFWI_TZ;
+constexpr bool SRCLOOP = PMLFWI_SRCLOOP;
+constexpr int ETHREADS = 256;           // threads per element workgroup
 
 fwi_status fail(fwi_plan* p, fwi_status s, const std::string& msg) {
   if (p) p->err = msg;
@@ -123,6 +140,55 @@ void build_tiles(fwi_plan* p) {
         if (a.interior && b.interior && c.interior) p->tiles_int.push_back(t);
         else p->tiles_pml.push_back(t);
       }
+  // upper faces of the lattice, numbered in increasing order per axis
+  const int nt = g.NX + g.NY + g.NZ;
+  p->fo.assign(nt, -1);
+  const std::vector<Seg>* segs[3] = {&sx, &sy, &sz};
+  const int off[3] = {0, g.NX, g.NX + g.NY};
+  for (int d = 0; d < 3; ++d) {
+    std::vector<int> faces;
+    for (auto& a : *segs[d]) faces.push_back(2 * (a.start + a.count));
+    std::sort(faces.begin(), faces.end());
+    for (size_t f = 0; f < faces.size(); ++f) p->fo[off[d] + faces[f]] = (int)f;
+    p->nface[d] = (int)faces.size();
+  }
+  // per-axis PML profile and lumped-mass factors (double, host)
+  p->tab.assign(4 * (size_t)nt, 0.0);
+  for (int l = 0; l < g.NX; ++l) {
+    stretch(g, fabs(g.x0 + 0.5 * g.h * l) - g.hx, g.Lps, p->tab[l], p->tab[nt + l]);
+    p->tab[2 * nt + l] = mass1d(l, 0, g.EX);
+    p->tab[3 * nt + l] = mass1d(l, g.ps, g.ps + g.ex);
+  }
+  for (int l = 0; l < g.NY; ++l) {
+    const int o = g.NX + l;
+    stretch(g, fabs(g.y0 + 0.5 * g.h * l) - g.hy, g.Lps, p->tab[o], p->tab[nt + o]);
+    p->tab[2 * nt + o] = mass1d(l, 0, g.EY);
+    p->tab[3 * nt + o] = mass1d(l, g.ps, g.ps + g.ey);
+  }
+  for (int l = 0; l < g.NZ; ++l) {
+    const int o = g.NX + g.NY + l;
+    stretch(g, -(g.z0 + 0.5 * g.h * l) - g.hz, g.Lpb, p->tab[o], p->tab[nt + o]);
+    p->tab[2 * nt + o] = mass1d(l, 0, g.EZ);
+    p->tab[3 * nt + o] = mass1d(l, g.pb, g.EZ);
+  }
+}
+
+// Partial-array layouts: residual (9 rows per node) and gradient (2 per node).
+Part part_layout(const Geo& g, const int nface[3], int rows, bool pml_compact0) {
+  Part P{};
+  long long o = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int nx = (c & 1) ? nface[0] : g.NX;
+    const int ny = (c & 2) ? nface[1] : g.NY;
+    const int nz = (c & 4) ? nface[2] : g.NZ;
+    P.nx[c] = nx;
+    P.ny[c] = ny;
+    P.size[c] = (long long)nx * ny * nz;
+    P.off[c] = o;
+    o += (c == 0 && pml_compact0) ? 3LL * g.n_nodes + 6LL * g.n_pml : (long long)rows * P.size[c];
+  }
+  P.per_src = o;
+  return P;
 }
 
 // ---------------------------------------------------------------- sizes
@@ -132,13 +198,23 @@ struct Layout {
   size_t res_elems;   // residual, one source
   size_t stage_elems; // stored stage displacement, all sources
   int nreg, nstore, nckpt;
-  size_t off_lam, off_mu, off_invm, off_regs, off_res, off_store, off_ckpt, total;
+  size_t off_lam, off_mu, off_invm, off_regs, off_res, off_gacc, off_store, off_ckpt, total;
+  Part part, gpart;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+int count_faces(const fwi_problem& P, const Geo& g, int d) {
+  if (d == 0) return (int)axis_segments(g.ps, g.ex, g.ps, TX).size();
+  if (d == 1) return (int)axis_segments(g.ps, g.ey, g.ps, TY).size();
+  return (int)axis_segments(g.pb, g.ez, 0, TZ).size();
+}
+
 Layout layout(const fwi_problem& P, const Geo& g) {
   Layout L{};
+  const int nface[3] = {count_faces(P, g, 0), count_faces(P, g, 1), count_faces(P, g, 2)};
+  L.part = part_layout(g, nface, 9, true);
+  L.gpart = part_layout(g, nface, 2, false);
   L.es = P.precision == FWI_FP32 ? 4 : 8;
   L.reg_elems = (size_t)U_NCOMP * g.n_nodes + (size_t)P_NCOMP * g.n_pml;
   L.res_elems = 3 * (size_t)g.n_nodes + 6 * (size_t)g.n_pml;
@@ -152,7 +228,8 @@ Layout layout(const fwi_problem& P, const Geo& g) {
   L.off_mu = o; o = align256(o + (size_t)g.n_int * L.es);
   L.off_invm = o; o = align256(o + (size_t)g.n_nodes * L.es);
   L.off_regs = o; o = align256(o + (size_t)L.nreg * P.nsrc * L.reg_elems * L.es);
-  L.off_res = o; o = align256(o + (size_t)P.nsrc * L.res_elems * L.es);
+  L.off_res = o; o = align256(o + (size_t)P.nsrc * L.part.per_src * L.es);
+  L.off_gacc = o; o = align256(o + (size_t)L.gpart.per_src * sizeof(double));
   L.off_store = o; o = align256(o + (size_t)L.nstore * 4 * L.stage_elems * L.es);
   L.off_ckpt = o; o = align256(o + (size_t)L.nckpt * P.nsrc * L.reg_elems * L.es);
   L.total = o;
@@ -245,6 +322,25 @@ __global__ void extract_kernel(Geo g, const R* __restrict__ X, long long reg, R*
     S[(size_t)src * sstr + (size_t)d * g.n_int + mi] = X[(size_t)src * reg + (size_t)d * g.n_nodes + node];
 }
 
+// g = sum of the gradient accumulator slots that can hold a contribution.
+__global__ void gradient_reduce_kernel(Geo g, const double* __restrict__ gacc, Part PG,
+                                       double* __restrict__ g_lam, double* __restrict__ g_mu) {
+  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mi >= g.n_int) return;
+  const int jz = mi / (g.NIX * g.NIY), rr = mi - jz * g.NIX * g.NIY, jy = rr / g.NIX, jx = rr - jy * g.NIX;
+  const int i = jx + 2 * g.ps, j = jy + 2 * g.ps, k = jz + 2 * g.pb;
+  const int mask = face_mask(g, i, j, k);
+  size_t o = (size_t)PG.off[0] + part_node(g, PG, 0, i, j, k);
+  double a = gacc[o], b = gacc[o + PG.size[0]];
+  for (int c = mask; c; c = (c - 1) & mask) {
+    o = (size_t)PG.off[c] + part_node(g, PG, c, i, j, k);
+    a += gacc[o];
+    b += gacc[o + PG.size[c]];
+  }
+  g_lam[mi] = a;
+  g_mu[mi] = b;
+}
+
 // Nodal test fields [nsrc][9][n_nodes] <-> register slot (0: x0, 1: x1, 2: x2).
 template <typename R>
 __global__ void pack_kernel(Geo g, const double* __restrict__ in, R* __restrict__ X, long long reg, int slot) {
@@ -271,25 +367,26 @@ __global__ void pack_kernel(Geo g, const double* __restrict__ in, R* __restrict_
 // out = -M^{-1}(r + nodal PML terms) for the register Y, nodal layout.
 template <typename R>
 __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, const R* __restrict__ res,
-                             long long rstr, const R* __restrict__ invMu, double* __restrict__ out) {
+                             Part PT, const R* __restrict__ invMu, double* __restrict__ out) {
   const int node = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
   if (node >= g.n_nodes) return;
   const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
   const size_t nn = g.n_nodes, np = g.n_pml;
   const R* U = Y + (size_t)src * reg;
   const R* P = U + 6 * nn;
-  const R* rs = res + (size_t)src * rstr;
+  const R* rs = res + (size_t)src * PT.per_src;
   double* O = out + (size_t)src * 9 * nn;
   const bool dir = is_dirichlet(g, i, j, k), pml = in_pml(g, i, j, k);
   for (int c = 0; c < 9; ++c) O[c * nn + node] = 0.0;
   double mrd, mp;
-  lumped_masses(g, i, j, k, mrd, mp);
-  const PmlCoef cf = pml_coef(g, i, j, k);
+  lumped_masses_tab(g, i, j, k, mrd, mp);
+  const PmlCoef cf = pml_coef_tab(g, i, j, k);
   const size_t p = pml ? (size_t)pml_index(g, i, j, k) : 0;
   const bool hist = cf.nbeta >= 2;
+  const PartSlots PS = part_slots(g, PT, i, j, k);
   if (!dir) {
     for (int d = 0; d < 3; ++d) {
-      double a = -(double)invMu[node] * (double)rs[d * nn + node];
+      double a = -(double)invMu[node] * (double)gather_rows(PT, PS, rs, (size_t)d * nn + node, d);
       if (pml) {
         const double kap = mp / (mrd + cf.a * mp);
         const double u0 = hist ? (double)P[(P_X0U + d) * np + p] : 0.0;
@@ -301,7 +398,7 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
   if (pml) {
     for (int v = 0; v < 6; ++v) {
       const double s0 = hist ? (double)P[(P_X0S + v) * np + p] : 0.0;
-      O[(3 + v) * nn + node] = -(double)rs[3 * nn + v * np + p] / (cf.a * mp) -
+      O[(3 + v) * nn + node] = -(double)gather_rows(PT, PS, rs, 3 * nn + (size_t)v * np + p, 3 + v) / (cf.a * mp) -
                                (cf.b * (double)P[(P_X2S + v) * np + p] + cf.c * (double)P[(P_X1S + v) * np + p] +
                                 cf.d * s0) / cf.a;
     }
@@ -323,6 +420,7 @@ struct Run {
   R* invm() const { return (R*)(ws + L.off_invm); }
   R* reg(int r) const { return (R*)(ws + L.off_regs) + (size_t)r * p->nsrc * L.reg_elems; }
   R* res() const { return (R*)(ws + L.off_res); }
+  double* gacc() const { return (double*)(ws + L.off_gacc); }
   R* store(int nl, int s) const {
     return (R*)(ws + L.off_store) + ((size_t)nl * 4 + s) * L.stage_elems;
   }
@@ -346,26 +444,31 @@ struct Run {
     return FWI_OK;
   }
 
-  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw, double* gl, double* gm) {
+  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw) {
     const Geo& G = g();
-    const long long reg = (long long)L.reg_elems, rs = (long long)L.res_elems;
+    const long long reg = (long long)L.reg_elems;
+    const int ns = p->nsrc;
     if (!p->tiles_int.empty()) {
-      dim3 grid((unsigned)p->tiles_int.size(), p->nsrc);
+      const int nt = (int)p->tiles_int.size();
+      const unsigned gx = 8u * (unsigned)((nt + 7) / 8);
       TimedLaunch tl(p, fwd ? FWI_K_INTERIOR_ADJ : FWI_K_INTERIOR, st);
       if (fwd)
-        interior_element_kernel<R, TX, TY, TZ, true><<<grid, 128, 0, st>>>(
-            G, p->d_tiles_int, Y, reg, lam(), mu(), res(), rs, fwd, 3LL * G.n_int, gw, gl, gm);
+        interior_element_kernel<R, TX, TY, TZ, true, true><<<dim3(gx, 1), ETHREADS, 0, st>>>(
+            G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, fwd, 3LL * G.n_int, gw, gacc(), L.gpart);
       else
-        interior_element_kernel<R, TX, TY, TZ, false><<<grid, 128, 0, st>>>(
-            G, p->d_tiles_int, Y, reg, lam(), mu(), res(), rs, nullptr, 0, 0.0, nullptr, nullptr);
+        interior_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<dim3(gx, SRCLOOP ? 1 : ns), ETHREADS, 0, st>>>(
+            G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, nullptr, 0, 0.0, nullptr, L.gpart);
     }
     if (!p->tiles_pml.empty()) {
-      dim3 grid((unsigned)p->tiles_pml.size(), p->nsrc);
+      const int nt = (int)p->tiles_pml.size();
+      const dim3 grid(8u * (unsigned)((nt + 7) / 8), SRCLOOP ? 1 : ns);
       TimedLaunch tl(p, adj ? FWI_K_PML_ADJ : FWI_K_PML, st);
       if (adj)
-        pml_element_kernel<R, TX, TY, TZ, true><<<grid, 128, 0, st>>>(G, p->d_tiles_pml, Y, reg, lam(), mu(), res(), rs);
+        pml_element_kernel<R, TX, TY, TZ, true, SRCLOOP><<<grid, ETHREADS, 0, st>>>(G, p->d_tiles_pml, nt, ns, Y, reg,
+                                                                                    lam(), mu(), res(), L.part);
       else
-        pml_element_kernel<R, TX, TY, TZ, false><<<grid, 128, 0, st>>>(G, p->d_tiles_pml, Y, reg, lam(), mu(), res(), rs);
+        pml_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<grid, ETHREADS, 0, st>>>(G, p->d_tiles_pml, nt, ns, Y, reg,
+                                                                                     lam(), mu(), res(), L.part);
     }
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
@@ -379,7 +482,8 @@ struct Run {
     const double dt = p->prob.dt;
     NodalArgs<R> A{};
     A.Yin = Yin; A.Yout = Yout; A.Xn = Xn; A.acc = acc; A.res = res(); A.invMu = invm();
-    A.reg = (long long)L.reg_elems; A.rstr = (long long)L.res_elems;
+    A.part = L.part;
+    A.reg = (long long)L.reg_elems;
     A.cA = R(cA[s] * dt); A.cY = R(cY[s] * dt);
     A.mode = s == 0 ? 0 : (s == 3 ? 2 : 1);
     if (wav) {
@@ -400,7 +504,7 @@ struct Run {
   // displacements of this step to store slot store_nl (and the next step's
   // first stage to store_nl+1 when store_next).
   fwi_status step(bool adj, int r0, int n, const double* wav, int store_nl, bool store_next,
-                  int fwd_nl, double* gl, double* gm) {
+                  int fwd_nl) {
     static const double bw[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
     R* Xn = reg(r0);
     R* Ya = reg(r0 + 1);
@@ -410,7 +514,7 @@ struct Run {
     R* outs[4] = {Ya, Yb, Ya, nullptr};
     for (int s = 0; s < 4; ++s) {
       const R* fwd = fwd_nl >= 0 ? store(fwd_nl, 3 - s) : nullptr;
-      fwi_status e = elements(adj, in, fwd, -bw[s] * p->prob.dt, gl, gm);
+      fwi_status e = elements(adj, in, fwd, -bw[s] * p->prob.dt);
       if (e != FWI_OK) return e;
       R* st_ = nullptr;
       if (store_nl >= 0) {
@@ -427,7 +531,7 @@ struct Run {
   fwi_status zero_regs(int r0, int nr) {
     fwi_status e = fill<R>(reg(r0), (size_t)nr * p->nsrc * L.reg_elems, R(0));
     if (e != FWI_OK) return e;
-    return fill<R>(res(), (size_t)p->nsrc * L.res_elems, R(0));
+    return fill<R>(res(), (size_t)p->nsrc * L.part.per_src, R(0));
   }
 
   fwi_status extract(const R* X, R* S) {
@@ -451,7 +555,7 @@ struct Run {
       if (!keep_all && n % P.ckpt_every == 0)
         HIP_TRY(p, hipMemcpyAsync(ckpt(n / P.ckpt_every), reg(0), (size_t)P.nsrc * L.reg_elems * L.es,
                                   hipMemcpyDeviceToDevice, st));
-      if ((e = step(false, 0, n, wav, keep_all ? n : -1, n + 1 < P.nsteps, -1, nullptr, nullptr)) != FWI_OK)
+      if ((e = step(false, 0, n, wav, keep_all ? n : -1, n + 1 < P.nsteps, -1)) != FWI_OK)
         return e;
       if (p->nrec > 0) {
         receivers_kernel<R><<<dim3(blocks(p->nrec, 128), P.nsrc), 128, 0, st>>>(
@@ -478,8 +582,7 @@ struct Run {
     const Geo& G = g();
     fwi_status e;
     if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
-    if ((e = fill<double>(gl, G.n_int, 0.0)) != FWI_OK) return e;
-    if ((e = fill<double>(gm, G.n_int, 0.0)) != FWI_OK) return e;
+    if ((e = fill<double>(gacc(), (size_t)L.gpart.per_src, 0.0)) != FWI_OK) return e;
     const bool keep_all = P.ckpt_every == 0;
     const int ra = keep_all ? 0 : 4;          // adjoint registers
     if ((e = zero_regs(ra, 4)) != FWI_OK) return e;
@@ -493,13 +596,15 @@ struct Run {
                                   hipMemcpyDeviceToDevice, st));
         if ((e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
         for (int n = a; n < b; ++n)
-          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1, nullptr, nullptr)) != FWI_OK) return e;
+          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
       }
       for (int n = b - 1; n >= a; --n) {
-        if ((e = step(true, ra, n, nullptr, -1, false, n - a, gl, gm)) != FWI_OK) return e;
+        if ((e = step(true, ra, n, nullptr, -1, false, n - a)) != FWI_OK) return e;
         if (n > 0 && (e = impulse(ra, resid, n)) != FWI_OK) return e;
       }
     }
+    gradient_reduce_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
+    HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
 
@@ -514,11 +619,11 @@ struct Run {
       pack_kernel<R><<<dim3(blocks(G.n_nodes, 256), p->nsrc), 256, 0, st>>>(G, xs[s], reg(0), (long long)L.reg_elems, s);
       HIP_TRY(p, hipGetLastError());
     }
-    if ((e = elements(which == 1, reg(0), nullptr, 0.0, nullptr, nullptr)) != FWI_OK) return e;
-    accel_kernel<R><<<dim3(blocks(G.n_nodes, 256), p->nsrc), 256, 0, st>>>(G, reg(0), (long long)L.reg_elems, res(),
-                                                                          (long long)L.res_elems, invm(), out);
+    if ((e = elements(which == 1, reg(0), nullptr, 0.0)) != FWI_OK) return e;
+    accel_kernel<R><<<dim3(blocks(G.n_nodes, 256), p->nsrc), 256, 0, st>>>(
+        G, reg(0), (long long)L.reg_elems, res(), L.part, invm(), out);
     HIP_TRY(p, hipGetLastError());
-    return fill<R>(res(), (size_t)p->nsrc * L.res_elems, R(0));
+    return FWI_OK;
   }
 };
 
@@ -593,6 +698,10 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   if (e == hipSuccess) e = up((void**)&p->d_src, src_node, prob->nsrc * sizeof(int32_t));
   if (e == hipSuccess) e = up((void**)&p->d_dir, src_dir, prob->nsrc * 3 * sizeof(double));
   if (e == hipSuccess) e = up((void**)&p->d_rec, rec_node, prob->nrec * sizeof(int32_t));
+  if (e == hipSuccess) e = up((void**)&p->d_tab, p->tab.data(), p->tab.size() * sizeof(double));
+  if (e == hipSuccess) e = up((void**)&p->d_fo, p->fo.data(), p->fo.size() * sizeof(int));
+  p->g.tab = p->d_tab;
+  p->g.fo = p->d_fo;
   if (e != hipSuccess) {
     fwi_plan_destroy(p);
     return FWI_ERR_HIP;
@@ -639,6 +748,8 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
   (void)hipFree(p->d_src);
   (void)hipFree(p->d_dir);
   (void)hipFree(p->d_rec);
+  (void)hipFree(p->d_tab);
+  (void)hipFree(p->d_fo);
   delete p;
   return FWI_OK;
 }
