@@ -158,6 +158,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl, n_state)
 
     line = {

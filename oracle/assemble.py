@@ -188,19 +188,16 @@ class System:
         self.n_X = self.n_hist + 2 * n
 
     # ------------------------------------------------------------------
-    def receiver_dofs(self, rec_node):
-        d = self.mesh.u_dof[np.asarray(rec_node)]
-        assert np.all(d >= 0), "receiver on a Dirichlet node"
-        return d                                    # (nrec, 3)
+    def residual(self, x0, x1, x2):
+        """G x0 + K x1 + C x2 (x0 on the history dofs)."""
+        return self.G @ x0 + self.K @ x1 + self.C @ x2
 
-    def source_vectors(self, src_node, src_dir):
-        """Unit-amplitude nodal force vectors, one column per source."""
-        F = np.zeros((self.n_state, len(src_node)))
-        for s, (nd, dv) in enumerate(zip(src_node, src_dir)):
-            d = self.mesh.u_dof[nd]
-            assert np.all(d >= 0), "source on a Dirichlet node"
-            F[d, s] += dv
-        return F
+    def residual_T3(self, z):
+        """(G^T z, K^T z, C^T z); G^T z lives on the history dofs."""
+        if not hasattr(self, "_T"):
+            self._T = (self.G.T.tocsr(), self.K.T.tocsr(), self.C.T.tocsr())
+        GT, KT, CT = self._T
+        return GT @ z, KT @ z, CT @ z
 
 
 def free_box_stiffness(ne, h, lam_fn, mu_fn, rho=1.0):

@@ -59,3 +59,26 @@ def coefficients(mesh, alpha0, beta0, m):
     return dict(Le=Lam[:, :, 0], Lp=Lam[:, :, 1], Lw=Lam[:, :, 2],
                 a=abcd[:, 0], b=abcd[:, 1], c=abcd[:, 2], d=abcd[:, 3],
                 alpha=alpha, beta=beta)
+
+
+def _pmul(p, q):
+    """Row-wise product of polynomials given as coefficient arrays (n, dp), (n, dq)."""
+    out = np.zeros((p.shape[0], p.shape[1] + q.shape[1] - 1))
+    for i in range(p.shape[1]):
+        for j in range(q.shape[1]):
+            out[:, i + j] += p[:, i] * q[:, j]
+    return out
+
+
+def coefficients_fast(mesh, alpha0, beta0, m):
+    """Same coefficients as ``coefficients``, the products taken for all nodes at once."""
+    alpha, beta = stretch_params(mesh, alpha0, beta0, m)
+    eps = [np.stack([alpha[:, s], beta[:, s]], axis=1) for s in range(3)]
+    full = _pmul(_pmul(eps[0], eps[1]), eps[2])
+    Lam = np.zeros((alpha.shape[0], 3, 3))
+    for k in range(3):
+        o = [s for s in range(3) if s != k]
+        Lam[:, k, :] = _pmul(eps[o[0]], eps[o[1]])
+    return dict(Le=Lam[:, :, 0], Lp=Lam[:, :, 1], Lw=Lam[:, :, 2],
+                a=full[:, 0], b=full[:, 1], c=full[:, 2], d=full[:, 3],
+                alpha=alpha, beta=beta)

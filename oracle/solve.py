@@ -27,18 +27,35 @@ from __future__ import annotations
 import numpy as np
 
 
+def source_vectors(mesh, n_state, src_node, src_dir):
+    """Unit-amplitude nodal force vectors, one column per source."""
+    F = np.zeros((n_state, len(src_node)))
+    for s, (nd, dv) in enumerate(zip(src_node, src_dir)):
+        d = mesh.u_dof[nd]
+        assert np.all(d >= 0), "source on a Dirichlet node"
+        F[d, s] += dv
+    return F
+
+
+def receiver_dofs(mesh, rec_node):
+    d = mesh.u_dof[np.asarray(rec_node)]
+    assert np.all(d >= 0), "receiver on a Dirichlet node"
+    return d                                    # (nrec, 3)
+
+
 class Stepper:
+    """RK4, misfit and adjoints for an operator object with ``residual``,
+    ``residual_T3``, ``Minv``, ``hist``, ``mesh``, ``g`` (the assembled
+    ``System`` or the element-batched ``MatFree``)."""
+
     def __init__(self, system, src_node, src_dir, rec_node):
         s = system
         self.s = s
         self.dt = s.prob.dt
         self.N = s.prob.nsteps
         self.nh, self.ns = s.n_hist, s.n_state
-        self.Fsrc = s.source_vectors(src_node, src_dir)         # (n_state, nsrc)
-        self.rec = s.receiver_dofs(rec_node)                     # (nrec, 3)
-        self.GT = s.G.T.tocsr()
-        self.KT = s.K.T.tocsr()
-        self.CT = s.C.T.tocsr()
+        self.Fsrc = source_vectors(s.mesh, s.n_state, src_node, src_dir)   # (n_state, nsrc)
+        self.rec = receiver_dofs(s.mesh, rec_node)                          # (nrec, 3)
 
     # -- X is (n_X, nsrc): [x0 (n_hist); x1 (n_state); x2 (n_state)]
     def split(self, X):
@@ -48,7 +65,7 @@ class Stepper:
     def rhs(self, X, f):
         s = self.s
         x0, x1, x2 = self.split(X)
-        acc = s.Minv[:, None] * (self.Fsrc * f[None, :] - s.G @ x0 - s.K @ x1 - s.C @ x2)
+        acc = s.Minv[:, None] * (self.Fsrc * f[None, :] - s.residual(x0, x1, x2))
         return np.concatenate([x1[s.hist], x2, acc], axis=0)
 
     def rhs_T(self, k):
@@ -56,10 +73,11 @@ class Stepper:
         s = self.s
         k0, k1, k2 = self.split(k)
         z = s.Minv[:, None] * k2
-        y0 = -(self.GT @ z)
-        y1 = -(self.KT @ z)
+        GT, KT, CT = s.residual_T3(z)
+        y0 = -GT
+        y1 = -KT
         y1[s.hist] += k0
-        y2 = k1 - self.CT @ z
+        y2 = k1 - CT
         return np.concatenate([y0, y1, y2], axis=0)
 
     def stages(self, X, wav, n):
@@ -210,8 +228,10 @@ class Stepper:
             # G^T here maps PML-history vectors to state vectors: transpose of
             # the PML x PML block of G, extended by zero outside the PML.
             ghat = np.zeros((ns, nsrc))
-            ghat[s.hist] = (s.G[s.hist, :].T @ y0)
-            acc = s.Minv[:, None] * (ghat - self.KT @ y1 + self.CT @ y2) + f
+            ext = np.zeros((ns, nsrc))
+            ext[s.hist] = y0
+            ghat[s.hist] = s.residual_T3(ext)[0]
+            acc = s.Minv[:, None] * (ghat - s.residual_T3(y1)[1] + s.residual_T3(y2)[2]) + f
             return y1[s.hist], y2, acc
 
         y0 = np.zeros((nh, nsrc))
