@@ -12,10 +12,18 @@ One bench step = one pass of the whole hot path on that batch: forward solve
 
 Usage: python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
                        [--ckpt k] [--nsteps N] [--no-cpu-baseline]
+                       [--copy-probe-mib MiB]
+
+--copy-probe-mib runs one plain element-wise copy of that size after the timed
+region; hardware-counter runs use it to scale FETCH_SIZE / WRITE_SIZE.  The
+roofline ``traffic`` field is read from the counter summary committed under
+profiles/ and reported only while the kernel sources hash to the value
+recorded there.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +35,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+CSRC = os.path.join(ROOT, "paper_1504_08340_amd", "csrc")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic__kernels__cfg40x40x20_4src_fp32.md")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources, in name order."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(cls, precision):
+    """Scaled HBM bytes per launch of a kernel class from the counter summary.
+
+    The summary holds lines ``traffic <class> <precision> <bytes>`` and one
+    ``source_sha256 <hex>`` line; None when the file is absent, the class is not
+    listed, or the sources changed since the counters were taken.
+    """
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            lines = [ln.split() for ln in f if ln.strip()]
+    except OSError:
+        return None
+    sha = [ln[1] for ln in lines if len(ln) == 2 and ln[0] == "source_sha256"]
+    if not sha or sha[0] != kernel_source_hash():
+        return None
+    for ln in lines:
+        if len(ln) == 4 and ln[0] == "traffic" and ln[1] == cls and ln[2] == precision:
+            return float(ln[3])
+    return None
 
 
 def history_nodes(prob):
@@ -87,6 +127,7 @@ def main():
     ap.add_argument("--nsteps", type=int, default=2000)
     ap.add_argument("--timing-stride", type=int, default=7)   # odd: samples every RK4 stage mode
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,6 +189,14 @@ def main():
             kstats[name] = dict(mean_ms=mean_ms, samples=samples, launches=launches,
                                 total_ms=mean_ms * launches / args.steps)
     P.fwi_timing_enable(S.plan, 0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * 2**20 // 4
+        src = torch.ones(n, dtype=torch.float32, device=S.device)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)          # reads and writes copy_probe_mib MiB once
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"# copy probe: {args.copy_probe_mib} MiB read + written", file=sys.stderr, flush=True)
     dom = max(kstats, key=lambda k: kstats[k]["total_ms"])
     alg = algorithmic_bytes(dom, S.sizes, prob, wl.nsrc, es)
     achieved = alg / (kstats[dom]["mean_ms"] * 1e-3) / 1e9
@@ -183,7 +232,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": recorded_traffic(dom, args.precision),
             "mean_launch_us": kstats[dom]["mean_ms"] * 1e3,
             "algorithmic_bytes_per_launch": alg,
         },
@@ -198,7 +248,7 @@ def cpu_baseline(wl, n_state):
         from oracle import matfree  # noqa: F401
     except ImportError:
         return None
-    return matfree.bench_sample(wl, n_state)
+    return matfree.bench_sample(wl, n_state, fwd_steps=2, adj_steps=2)
 
 
 if __name__ == "__main__":
