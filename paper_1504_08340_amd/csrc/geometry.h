@@ -25,6 +25,9 @@ struct Geo {
   int NIX, NIY, NIZ;     // interior-closure node grid
   int w, zb;             // frame width (nodes), last complete PML plane
   int n_nodes, n_pml, n_int;
+  int sn, sp, si;        // component strides of the three index spaces: the
+                         // counts rounded up to 64 entries, so that every
+                         // component array starts on a 256-byte boundary
   int plane, ring;       // NX*NY, nodes of one frame plane
   double h;
   double x0, y0, z0;     // coordinates of node (0,0,0)

@@ -72,12 +72,12 @@ __device__ __forceinline__ size_t part_node(const Geo& g, const Part& P, int c, 
 // Offset of u-row d / S-row v of a node in partial array c (within one source).
 __device__ __forceinline__ size_t part_u(const Geo& g, const Part& P, int c, int i, int j, int k,
                                          size_t node, int d) {
-  if (c == 0) return (size_t)d * g.n_nodes + node;
+  if (c == 0) return (size_t)d * g.sn + node;
   return (size_t)P.off[c] + (size_t)d * P.size[c] + part_node(g, P, c, i, j, k);
 }
 __device__ __forceinline__ size_t part_s(const Geo& g, const Part& P, int c, int i, int j, int k,
                                          size_t p, int v) {
-  if (c == 0) return 3 * (size_t)g.n_nodes + (size_t)v * g.n_pml + p;
+  if (c == 0) return 3 * (size_t)g.sn + (size_t)v * g.sp + p;
   return (size_t)P.off[c] + (3 + (size_t)v) * P.size[c] + part_node(g, P, c, i, j, k);
 }
 
@@ -147,7 +147,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
   const Tile t = tiles[ti];
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
   const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
-  const size_t nn = (size_t)g.n_nodes;
+  const size_t nn = (size_t)g.sn;
   const R s2h = R(2.0 / g.h);
 
   for (int n = threadIdx.x; n < NB; n += blockDim.x) {
@@ -177,7 +177,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
         const R* F = fwd + (size_t)src * fstride;
         const int mi = interior_index(g, i, j, k);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sV[d][n] = F[(size_t)d * g.n_int + mi];
+        for (int d = 0; d < 3; ++d) sV[d][n] = F[(size_t)d * g.si + mi];
       }
     }
     __syncthreads();
@@ -324,7 +324,7 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   const Tile t = tiles[ti];
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
   const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
-  const size_t nn = (size_t)g.n_nodes, np = (size_t)g.n_pml;
+  const size_t nn = (size_t)g.sn, np = (size_t)g.sp;
   const R s2h = R(2.0 / g.h);
   const R vol = R(0.125 * g.h * g.h * g.h);
 
@@ -517,8 +517,6 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
 //   mode 0:  acc = Xn + cA K,  Yout = Xn + cY K
 //   mode 1:  acc += cA K,      Yout = Xn + cY K
 //   mode 2:  Xn = acc + cA K
-// Threads [0, n_nodes) handle the displacement rows, [n_nodes, n_nodes +
-// n_pml) the PML rows.
 template <typename R>
 struct NodalArgs {
   const R* Yin;
@@ -559,57 +557,81 @@ __device__ __forceinline__ PartSlots part_slots(const Geo& g, const Part& P, int
 }
 
 // Sum over the partial arrays of row `row` (0..2 u-rows, 3..8 S-rows); off0 is
-// the entry in array 0.
+// the entry in array 0.  The single-axis arrays (c = 1, 2, 4) are read
+// unconditionally, at entry 0 of the array when the node is not on that face,
+// and the value is discarded by a select: the loads then issue together with
+// the others instead of one branch at a time.  Nodes on two or three faces
+// (1/32 of the nodes or fewer per array) take a branch.
 template <typename R>
 __device__ __forceinline__ R gather_rows(const Part& P, const PartSlots& S, const R* res, size_t off0, int row) {
-  R s = res[off0];
+  R t[8];
+  t[0] = res[off0];
 #pragma unroll
-  for (int c = 1; c < 8; ++c)
-    if ((S.mask & c) == c) s += res[(size_t)P.off[c] + (size_t)row * P.size[c] + S.nc[c]];
+  for (int b = 0; b < 3; ++b) {
+    const int c = 1 << b;
+    const bool on = (S.mask & c) != 0;
+    const R v = res[(size_t)P.off[c] + (size_t)row * P.size[c] + (on ? S.nc[c] : 0)];
+    t[c] = on ? v : R(0);
+  }
+  R s = t[0] + t[1] + t[2] + t[4];
+  if (S.mask == 3 || S.mask == 5 || S.mask == 6 || S.mask == 7) {
+#pragma unroll
+    for (int c = 3; c < 8; ++c)
+      if (c != 4 && (S.mask & c) == c) s += res[(size_t)P.off[c] + (size_t)row * P.size[c] + S.nc[c]];
+  }
   return s;
 }
 
-template <typename R>
+// Nodal part of one stage for node rows and PML rows; MODE as described above,
+// STORE writes the produced x1 displacement on the interior closure.
+// Threads [0, sn) take the displacement rows of node gid (none past n_nodes),
+// threads [sn, sn + n_pml) the PML rows; every load of a thread is issued
+// before its first store.
+template <typename R, int MODE, bool STORE>
 __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nn = (size_t)g.n_nodes, np = (size_t)g.n_pml;
-  const R* Y = A.Yin + (size_t)src * A.reg;
-  R* Yo = A.Yout ? A.Yout + (size_t)src * A.reg : nullptr;
-  R* X = A.Xn + (size_t)src * A.reg;
-  R* C = A.acc + (size_t)src * A.reg;
-  const R* res = A.res + (size_t)src * A.part.per_src;
+  const size_t nn = (size_t)g.sn, np = (size_t)g.sp;
+  const R* __restrict__ Y = A.Yin + (size_t)src * A.reg;
+  R* __restrict__ Yo = MODE == 2 ? nullptr : A.Yout + (size_t)src * A.reg;
+  R* __restrict__ X = A.Xn + (size_t)src * A.reg;
+  R* __restrict__ C = A.acc + (size_t)src * A.reg;
+  const R* __restrict__ res = A.res + (size_t)src * A.part.per_src;
   const R cA = A.cA, cY = A.cY;
-  const int mode = A.mode;
 
   if (gid < (long long)nn) {
+    if (gid >= g.n_nodes) return;
     const int node = (int)gid;
     const int k = node / g.plane;
     const int r_ = node - k * g.plane;
     const int j = r_ / g.NX, i = r_ - j * g.NX;
     if (is_dirichlet(g, i, j, k)) return;
+    const bool pml = in_pml(g, i, j, k);
     const PartSlots PS = part_slots(g, A.part, i, j, k);
-    R u1[3], u2[3], rr[3], a2[3];
+    R u1[3], u2[3], rr[3], x1[3], x2[3], c1[3], c2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      u1[d] = Y[d * nn + node];
-      u2[d] = Y[(3 + d) * nn + node];
-      rr[d] = gather_rows(A.part, PS, res, (size_t)d * nn + node, d);
+      const size_t o1 = d * nn + node, o2 = (3 + d) * nn + node;
+      u1[d] = Y[o1];
+      u2[d] = Y[o2];
+      rr[d] = gather_rows(A.part, PS, res, o1, d);
+      if (MODE != 2) { x1[d] = X[o1]; x2[d] = X[o2]; }
+      if (MODE != 0) { c1[d] = C[o1]; c2[d] = C[o2]; }
     }
-    R f[3] = {0, 0, 0};
+    const R im = A.invMu[node];
+    R a2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a2[d] = -im * rr[d];
     if (A.src_node && A.src_node[src] == node) {
       const double s = A.wav[(size_t)src * A.wav_len + A.wav_idx];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) f[d] = R(A.src_dir[3 * src + d] * s);
+      for (int d = 0; d < 3; ++d) a2[d] += im * R(A.src_dir[3 * src + d] * s);
     }
-    const R im = A.invMu[node];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) a2[d] = im * (f[d] - rr[d]);
-    if (in_pml(g, i, j, k)) {
+    if (pml) {
       double mrd, mp;
       lumped_masses_tab(g, i, j, k, mrd, mp);
       const PmlCoef c = pml_coef_tab(g, i, j, k);
-      const R kap = R(mp / (mrd + c.a * mp));
+      const R kap = R(mp) / (R(mrd) + R(c.a) * R(mp));
       R u0[3] = {0, 0, 0};
       if (c.nbeta >= 2) {
         const size_t p = (size_t)pml_index(g, i, j, k);
@@ -625,34 +647,28 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const size_t o1 = d * nn + node, o2 = (3 + d) * nn + node;
-      if (mode == 2) {
-        X[o1] = out1[d] = C[o1] + cA * u2[d];
-        X[o2] = C[o2] + cA * a2[d];
+      if (MODE == 2) {
+        X[o1] = out1[d] = c1[d] + cA * u2[d];
+        X[o2] = c2[d] + cA * a2[d];
       } else {
-        const R x1 = X[o1], x2 = X[o2];
-        if (mode == 0) {
-          C[o1] = x1 + cA * u2[d];
-          C[o2] = x2 + cA * a2[d];
-        } else {
-          C[o1] += cA * u2[d];
-          C[o2] += cA * a2[d];
-        }
-        Yo[o1] = out1[d] = x1 + cY * u2[d];
-        Yo[o2] = x2 + cY * a2[d];
+        C[o1] = (MODE == 0 ? x1[d] : c1[d]) + cA * u2[d];
+        C[o2] = (MODE == 0 ? x2[d] : c2[d]) + cA * a2[d];
+        Yo[o1] = out1[d] = x1[d] + cY * u2[d];
+        Yo[o2] = x2[d] + cY * a2[d];
       }
     }
-    if (A.store) {
+    if (STORE) {
       const int mi = interior_index(g, i, j, k);
       if (mi >= 0) {
         R* S = A.store + (size_t)src * A.store_stride;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) S[(size_t)d * g.n_int + mi] = out1[d];
+        for (int d = 0; d < 3; ++d) S[(size_t)d * g.si + mi] = out1[d];
       }
     }
     return;
   }
   const long long pp = gid - (long long)nn;
-  if (pp >= (long long)np) return;
+  if (pp >= (long long)g.n_pml) return;
   const size_t p = (size_t)pp;
   int i, j, k;
   pml_coords(g, (int)p, i, j, k);
@@ -660,39 +676,56 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   double mrd, mp;
   lumped_masses_tab(g, i, j, k, mrd, mp);
   const bool hist = c.nbeta >= 2;
+  const bool hu = hist && !is_dirichlet(g, i, j, k);
   const R* PY = Y + 6 * nn;
   R* PX = X + 6 * nn;
   R* PC = C + 6 * nn;
-  R* PO = Yo ? Yo + 6 * nn : nullptr;
+  R* PO = MODE == 2 ? nullptr : Yo + 6 * nn;
   const PartSlots PS = part_slots(g, A.part, i, j, k);
-  const R ia = R(1.0 / c.a), iam = R(1.0 / (c.a * mp));
+  const R ia = R(1) / R(c.a), iam = R(1) / (R(c.a) * R(mp));
   const R cb = R(c.b), cc = R(c.c), cd = R(c.d);
 
-  auto upd = [&](int comp, R rate) {
-    const size_t o = (size_t)comp * np + p;
-    if (mode == 2) {
-      PX[o] = PC[o] + cA * rate;
-    } else {
-      const R x = PX[o];
-      if (mode == 0) PC[o] = x + cA * rate;
-      else PC[o] += cA * rate;
-      PO[o] = x + cY * rate;
-    }
-  };
+  // rates of the 21 PML components, then one pass of register updates
+  R rate[P_NCOMP], xv[P_NCOMP], cv[P_NCOMP];
+  R s0[6], s1[6], s2[6], rv[6], y1[3];
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
-    const R s1 = PY[(P_X1S + v) * np + p], s2 = PY[(P_X2S + v) * np + p];
-    const R s0 = hist ? PY[(P_X0S + v) * np + p] : R(0);
-    const R rv = gather_rows(A.part, PS, res, 3 * nn + (size_t)v * np + p, 3 + v);
-    const R a2 = -rv * iam - ia * (cb * s2 + cc * s1 + cd * s0);
-    if (hist) upd(P_X0S + v, s1);
-    upd(P_X1S + v, s2);
-    upd(P_X2S + v, a2);
+    s1[v] = PY[(P_X1S + v) * np + p];
+    s2[v] = PY[(P_X2S + v) * np + p];
+    s0[v] = hist ? PY[(P_X0S + v) * np + p] : R(0);
+    rv[v] = gather_rows(A.part, PS, res, 3 * nn + (size_t)v * np + p, 3 + v);
   }
-  if (hist && !is_dirichlet(g, i, j, k)) {
+  if (hu) {
     const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) upd(P_X0U + d, Y[d * nn + node]);
+    for (int d = 0; d < 3; ++d) y1[d] = Y[d * nn + node];
+  }
+#pragma unroll
+  for (int q = 0; q < P_NCOMP; ++q) {
+    const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
+    const size_t o = (size_t)q * np + p;
+    if (live && MODE != 2) xv[q] = PX[o];
+    if (live && MODE != 0) cv[q] = PC[o];
+  }
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    rate[P_X0S + v] = s1[v];
+    rate[P_X1S + v] = s2[v];
+    rate[P_X2S + v] = -rv[v] * iam - ia * (cb * s2[v] + cc * s1[v] + cd * s0[v]);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) rate[P_X0U + d] = hu ? y1[d] : R(0);
+#pragma unroll
+  for (int q = 0; q < P_NCOMP; ++q) {
+    const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
+    if (!live) continue;
+    const size_t o = (size_t)q * np + p;
+    if (MODE == 2) {
+      PX[o] = cv[q] + cA * rate[q];
+    } else {
+      PC[o] = (MODE == 0 ? xv[q] : cv[q]) + cA * rate[q];
+      PO[o] = xv[q] + cY * rate[q];
+    }
   }
 }
 

@@ -106,6 +106,9 @@ Geo make_geo(const fwi_problem& P) {
   g.n_nodes = g.plane * g.NZ;
   g.n_pml = (g.zb + 1) * g.plane + (g.NZ - g.zb - 1) * g.ring;
   g.n_int = g.NIX * g.NIY * g.NIZ;
+  g.sn = (g.n_nodes + 63) & ~63;
+  g.sp = (g.n_pml + 63) & ~63;
+  g.si = (g.n_int + 63) & ~63;
   g.h = P.h;
   g.hx = 0.5 * g.ex * P.h; g.hy = 0.5 * g.ey * P.h; g.hz = g.ez * P.h;
   g.Lps = g.ps * P.h; g.Lpb = g.pb * P.h;
@@ -183,9 +186,11 @@ Part part_layout(const Geo& g, const int nface[3], int rows, bool pml_compact0) 
     const int nz = (c & 4) ? nface[2] : g.NZ;
     P.nx[c] = nx;
     P.ny[c] = ny;
-    P.size[c] = (long long)nx * ny * nz;
+    // c != 0 strides rounded up to 64 entries (256-byte aligned rows); array 0
+    // of the residual uses the register index spaces
+    P.size[c] = c == 0 ? (long long)g.sn : (((long long)nx * ny * nz + 63) & ~63LL);
     P.off[c] = o;
-    o += (c == 0 && pml_compact0) ? 3LL * g.n_nodes + 6LL * g.n_pml : (long long)rows * P.size[c];
+    o += (c == 0 && pml_compact0) ? 3LL * g.sn + 6LL * g.sp : (long long)rows * P.size[c];
   }
   P.per_src = o;
   return P;
@@ -216,9 +221,9 @@ Layout layout(const fwi_problem& P, const Geo& g) {
   L.part = part_layout(g, nface, 9, true);
   L.gpart = part_layout(g, nface, 2, false);
   L.es = P.precision == FWI_FP32 ? 4 : 8;
-  L.reg_elems = (size_t)U_NCOMP * g.n_nodes + (size_t)P_NCOMP * g.n_pml;
-  L.res_elems = 3 * (size_t)g.n_nodes + 6 * (size_t)g.n_pml;
-  L.stage_elems = (size_t)P.nsrc * 3 * g.n_int;
+  L.reg_elems = (size_t)U_NCOMP * g.sn + (size_t)P_NCOMP * g.sp;
+  L.res_elems = 3 * (size_t)g.sn + 6 * (size_t)g.sp;
+  L.stage_elems = (size_t)P.nsrc * 3 * g.si;
   const int k = P.ckpt_every;
   L.nreg = k == 0 ? 4 : 8;
   L.nstore = k == 0 ? P.nsteps : std::min(k, P.nsteps);
@@ -265,7 +270,7 @@ __global__ void convert_kernel(const double* __restrict__ in, R* __restrict__ ou
 }
 
 template <typename R>
-__global__ void receivers_kernel(const R* __restrict__ X, long long reg, int n_nodes,
+__global__ void receivers_kernel(const R* __restrict__ X, long long reg, int sn,
                                  const int* __restrict__ rec, int nrec, double* __restrict__ traces,
                                  int step, int nsteps) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
@@ -273,12 +278,12 @@ __global__ void receivers_kernel(const R* __restrict__ X, long long reg, int n_n
   const R* U = X + (size_t)src * reg;
   double* T = traces + ((size_t)src * (nsteps + 1) + step) * nrec * 3 + (size_t)r * 3;
   const int node = rec[r];
-  for (int d = 0; d < 3; ++d) T[d] = (double)U[(size_t)d * n_nodes + node];
+  for (int d = 0; d < 3; ++d) T[d] = (double)U[(size_t)d * sn + node];
 }
 
 // Adjoint impulse after a reverse step: y2_u += M^{-1} dt w_n (u^n - u_m^n) at receivers.
 template <typename R>
-__global__ void impulse_kernel(R* __restrict__ Y, long long reg, int n_nodes, const R* __restrict__ invMu,
+__global__ void impulse_kernel(R* __restrict__ Y, long long reg, int sn, const R* __restrict__ invMu,
                                const int* __restrict__ rec, int nrec, const double* __restrict__ resid,
                                int step, int nsteps, double scale) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
@@ -287,7 +292,7 @@ __global__ void impulse_kernel(R* __restrict__ Y, long long reg, int n_nodes, co
   const double* E = resid + ((size_t)src * (nsteps + 1) + step) * nrec * 3 + (size_t)r * 3;
   const int node = rec[r];
   const R im = invMu[node];
-  for (int d = 0; d < 3; ++d) atomic_add(&U[(size_t)(3 + d) * n_nodes + node], R(scale * E[d]) * im);
+  for (int d = 0; d < 3; ++d) atomic_add(&U[(size_t)(3 + d) * sn + node], R(scale * E[d]) * im);
 }
 
 __global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ obs,
@@ -319,7 +324,7 @@ __global__ void extract_kernel(Geo g, const R* __restrict__ X, long long reg, R*
   const int jz = mi / (g.NIX * g.NIY), rr = mi - jz * g.NIX * g.NIY, jy = rr / g.NIX, jx = rr - jy * g.NIX;
   const size_t node = (size_t)(jx + 2 * g.ps) + (size_t)g.NX * ((jy + 2 * g.ps) + (size_t)g.NY * (jz + 2 * g.pb));
   for (int d = 0; d < 3; ++d)
-    S[(size_t)src * sstr + (size_t)d * g.n_int + mi] = X[(size_t)src * reg + (size_t)d * g.n_nodes + node];
+    S[(size_t)src * sstr + (size_t)d * g.si + mi] = X[(size_t)src * reg + (size_t)d * g.sn + node];
 }
 
 // g = sum of the gradient accumulator slots that can hold a contribution.
@@ -347,20 +352,20 @@ __global__ void pack_kernel(Geo g, const double* __restrict__ in, R* __restrict_
   const int node = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
   if (node >= g.n_nodes) return;
   const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
-  const size_t nn = g.n_nodes, np = g.n_pml;
-  const double* F = in + (size_t)src * 9 * nn;
+  const size_t nf = g.n_nodes, nn = g.sn, np = g.sp;
+  const double* F = in + (size_t)src * 9 * nf;
   R* U = X + (size_t)src * reg;
   R* P = U + 6 * nn;
   const bool dir = is_dirichlet(g, i, j, k), pml = in_pml(g, i, j, k);
   const size_t p = pml ? (size_t)pml_index(g, i, j, k) : 0;
   for (int d = 0; d < 3; ++d) {
-    const R v = dir ? R(0) : R(F[d * nn + node]);
+    const R v = dir ? R(0) : R(F[d * nf + node]);
     if (slot == 0) { if (pml) P[(P_X0U + d) * np + p] = v; }
     else U[(size_t)(slot == 1 ? d : 3 + d) * nn + node] = v;
   }
   if (pml) {
     const int base = slot == 0 ? P_X0S : (slot == 1 ? P_X1S : P_X2S);
-    for (int v = 0; v < 6; ++v) P[(base + v) * np + p] = R(F[(3 + v) * nn + node]);
+    for (int v = 0; v < 6; ++v) P[(base + v) * np + p] = R(F[(3 + v) * nf + node]);
   }
 }
 
@@ -371,13 +376,13 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
   const int node = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
   if (node >= g.n_nodes) return;
   const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
-  const size_t nn = g.n_nodes, np = g.n_pml;
+  const size_t nf = g.n_nodes, nn = g.sn, np = g.sp;
   const R* U = Y + (size_t)src * reg;
   const R* P = U + 6 * nn;
   const R* rs = res + (size_t)src * PT.per_src;
-  double* O = out + (size_t)src * 9 * nn;
+  double* O = out + (size_t)src * 9 * nf;
   const bool dir = is_dirichlet(g, i, j, k), pml = in_pml(g, i, j, k);
-  for (int c = 0; c < 9; ++c) O[c * nn + node] = 0.0;
+  for (int c = 0; c < 9; ++c) O[c * nf + node] = 0.0;
   double mrd, mp;
   lumped_masses_tab(g, i, j, k, mrd, mp);
   const PmlCoef cf = pml_coef_tab(g, i, j, k);
@@ -392,13 +397,13 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
         const double u0 = hist ? (double)P[(P_X0U + d) * np + p] : 0.0;
         a -= kap * (cf.b * (double)U[(3 + d) * nn + node] + cf.c * (double)U[d * nn + node] + cf.d * u0);
       }
-      O[d * nn + node] = a;
+      O[d * nf + node] = a;
     }
   }
   if (pml) {
     for (int v = 0; v < 6; ++v) {
       const double s0 = hist ? (double)P[(P_X0S + v) * np + p] : 0.0;
-      O[(3 + v) * nn + node] = -(double)gather_rows(PT, PS, rs, 3 * nn + (size_t)v * np + p, 3 + v) / (cf.a * mp) -
+      O[(3 + v) * nf + node] = -(double)gather_rows(PT, PS, rs, 3 * nn + (size_t)v * np + p, 3 + v) / (cf.a * mp) -
                                (cf.b * (double)P[(P_X2S + v) * np + p] + cf.c * (double)P[(P_X1S + v) * np + p] +
                                 cf.d * s0) / cf.a;
     }
@@ -454,7 +459,7 @@ struct Run {
       TimedLaunch tl(p, fwd ? FWI_K_INTERIOR_ADJ : FWI_K_INTERIOR, st);
       if (fwd)
         interior_element_kernel<R, TX, TY, TZ, true, true><<<dim3(gx, 1), ETHREADS, 0, st>>>(
-            G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, fwd, 3LL * G.n_int, gw, gacc(), L.gpart);
+            G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, fwd, 3LL * G.si, gw, gacc(), L.gpart);
       else
         interior_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<dim3(gx, SRCLOOP ? 1 : ns), ETHREADS, 0, st>>>(
             G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, nullptr, 0, 0.0, nullptr, L.gpart);
@@ -490,11 +495,14 @@ struct Run {
       A.src_node = p->d_src; A.src_dir = p->d_dir; A.wav = wav;
       A.wav_len = 2 * p->prob.nsteps + 1; A.wav_idx = 2 * step + toff[s];
     }
-    A.store = store; A.store_stride = 3LL * G.n_int;
-    dim3 grid(blocks((size_t)G.n_nodes + G.n_pml, 256), p->nsrc);
+    A.store = store; A.store_stride = 3LL * G.si;
+    dim3 grid(blocks((size_t)G.sn + G.n_pml, 256), p->nsrc);
     {
       TimedLaunch tl(p, FWI_K_NODAL, st);
-      nodal_rk_kernel<R><<<grid, 256, 0, st>>>(G, A);
+      auto kern = A.mode == 0 ? (store ? nodal_rk_kernel<R, 0, true> : nodal_rk_kernel<R, 0, false>)
+                : A.mode == 1 ? (store ? nodal_rk_kernel<R, 1, true> : nodal_rk_kernel<R, 1, false>)
+                              : (store ? nodal_rk_kernel<R, 2, true> : nodal_rk_kernel<R, 2, false>);
+      kern<<<grid, 256, 0, st>>>(G, A);
     }
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
@@ -536,7 +544,7 @@ struct Run {
 
   fwi_status extract(const R* X, R* S) {
     const Geo& G = g();
-    extract_kernel<R><<<dim3(blocks(G.n_int, 256), p->nsrc), 256, 0, st>>>(G, X, (long long)L.reg_elems, S, 3LL * G.n_int);
+    extract_kernel<R><<<dim3(blocks(G.n_int, 256), p->nsrc), 256, 0, st>>>(G, X, (long long)L.reg_elems, S, 3LL * G.si);
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
@@ -559,7 +567,7 @@ struct Run {
         return e;
       if (p->nrec > 0) {
         receivers_kernel<R><<<dim3(blocks(p->nrec, 128), P.nsrc), 128, 0, st>>>(
-            reg(0), (long long)L.reg_elems, g().n_nodes, p->d_rec, p->nrec, traces, n + 1, P.nsteps);
+            reg(0), (long long)L.reg_elems, g().sn, p->d_rec, p->nrec, traces, n + 1, P.nsteps);
         HIP_TRY(p, hipGetLastError());
       }
     }
@@ -571,7 +579,7 @@ struct Run {
     const fwi_problem& P = p->prob;
     const double w = (n == 0 || n == P.nsteps) ? 0.5 : 1.0;
     impulse_kernel<R><<<dim3(blocks(p->nrec, 128), P.nsrc), 128, 0, st>>>(
-        reg(r0), (long long)L.reg_elems, g().n_nodes, invm(), p->d_rec, p->nrec, resid, n, P.nsteps, P.dt * w);
+        reg(r0), (long long)L.reg_elems, g().sn, invm(), p->d_rec, p->nrec, resid, n, P.nsteps, P.dt * w);
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
