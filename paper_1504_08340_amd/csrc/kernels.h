@@ -69,16 +69,31 @@ __device__ __forceinline__ size_t part_node(const Geo& g, const Part& P, int c, 
   return (size_t)ii + (size_t)P.nx[c] * ((size_t)jj + (size_t)P.ny[c] * kk);
 }
 
-// Offset of u-row d / S-row v of a node in partial array c (within one source).
-__device__ __forceinline__ size_t part_u(const Geo& g, const Part& P, int c, int i, int j, int k,
-                                         size_t node, int d) {
-  if (c == 0) return (size_t)d * g.sn + node;
-  return (size_t)P.off[c] + (size_t)d * P.size[c] + part_node(g, P, c, i, j, k);
-}
-__device__ __forceinline__ size_t part_s(const Geo& g, const Part& P, int c, int i, int j, int k,
-                                         size_t p, int v) {
-  if (c == 0) return 3 * (size_t)g.sn + (size_t)v * g.sp + p;
-  return (size_t)P.off[c] + (3 + (size_t)v) * P.size[c] + part_node(g, P, c, i, j, k);
+// Offsets of a node's rows in partial array c (within one source): u-row d at
+// u + d * us, S-row v at s + v * ss.  Computed once per node before its
+// stores, so the lane-varying lookups of the array constants and face
+// ordinals are waited for once rather than once per row.
+struct RowAddr {
+  size_t u, us, s, ss;
+};
+
+__device__ __forceinline__ RowAddr row_addr(const Geo& g, const Part& P, int c, int i, int j, int k,
+                                            size_t node, size_t p) {
+  RowAddr a;
+  if (c == 0) {
+    a.u = node;
+    a.us = (size_t)g.sn;
+    a.s = 3 * (size_t)g.sn + p;
+    a.ss = (size_t)g.sp;
+    return a;
+  }
+  const size_t n = part_node(g, P, c, i, j, k);
+  const size_t size = (size_t)P.size[c];
+  a.u = (size_t)P.off[c] + n;
+  a.us = size;
+  a.s = a.u + 3 * size;
+  a.ss = size;
+  return a;
 }
 
 __device__ __forceinline__ int xcd_tile() {
@@ -273,9 +288,10 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
       const int c = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
       if (!is_dirichlet(g, i, j, k)) {
         const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
-        res[part_u(g, PT, c, i, j, k, node, 0)] = r0 * s2h;
-        res[part_u(g, PT, c, i, j, k, node, 1)] = r1 * s2h;
-        res[part_u(g, PT, c, i, j, k, node, 2)] = r2 * s2h;
+        const RowAddr ra = row_addr(g, PT, c, i, j, k, node, 0);
+        res[ra.u] = r0 * s2h;
+        res[ra.u + ra.us] = r1 * s2h;
+        res[ra.u + 2 * ra.us] = r2 * s2h;
       }
       if constexpr (GRAD) {
         sGacc[0][n] += (double)gl;
@@ -290,9 +306,10 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
       if (lx >= nbx || ly >= nby || lz >= nbz) continue;
       const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
       const int c = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
-      const size_t o = (size_t)PG.off[c] + part_node(g, PG, c, i, j, k);
-      gacc[o] += gw * sGacc[0][n];
-      gacc[o + PG.size[c]] += gw * sGacc[1][n];
+      const size_t o = (size_t)PG.off[c] + part_node(g, PG, c, i, j, k), gs = (size_t)PG.size[c];
+      const double a0 = gacc[o], a1 = gacc[o + gs];
+      gacc[o] = a0 + gw * sGacc[0][n];
+      gacc[o + gs] = a1 + gw * sGacc[1][n];
     }
   }
 }
@@ -498,13 +515,14 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
           }
       R* res = rbase + (size_t)src * PT.per_src;
       const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+      const RowAddr ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
 #pragma unroll
-      for (int v = 0; v < 6; ++v) res[part_s(g, PT, cs, gi, gj, gk, gp, v)] = q6[v];
+      for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
       if (!is_dirichlet(g, gi, gj, gk)) {
         const R f = vol * s2h;
 #pragma unroll
         for (int ii = 0; ii < 3; ++ii)
-          res[part_u(g, PT, cs, gi, gj, gk, gnode, ii)] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
+          res[ra.u + ii * ra.us] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
       }
     }
     __syncthreads();
