@@ -154,6 +154,31 @@ fwi_status fwi_apply_operator(fwi_plan* plan, void* stream, int which,
                               const double* x1, const double* x2,
                               void* workspace, double* out);
 
+/* Regularization of one nodal material field f (n_int_nodes FP64, closed
+ * interior, x fastest): kind FWI_REG_TIKHONOV, R(f) = 1/2 int |grad f|^2 (8),
+ * or FWI_REG_TV, R(f) = int (|grad f|^2 + eps)^(1/2) (9) with the pointwise
+ * denominator of (17) (the functional carries R, not R/2, so that (17) is its
+ * derivative).  LGL quadrature of every interior brick.  value (one double on
+ * the device) and grad (n_int_nodes: dR/df_j, the discrete vectors of
+ * (C.1b)-(C.1e)) are overwritten; either may be null.  Deterministic. */
+enum { FWI_REG_TIKHONOV = 0, FWI_REG_TV = 1 };
+fwi_status fwi_regularization(fwi_plan* plan, void* stream, int kind, double eps,
+                              const double* field, double* value, double* grad);
+
+/* M~ of (C.1a): the diagonal LGL mass of the closed interior (n_int_nodes). */
+fwi_status fwi_material_mass(fwi_plan* plan, void* stream, double* mdiag);
+
+/* Control problem (18): g = M~^{-1} (g_mis + R g_reg), n_int_nodes each;
+ * g_reg may be null when R = 0.  g may alias g_mis. */
+fwi_status fwi_gradient_finalize(fwi_plan* plan, void* stream, const double* g_mis,
+                                 const double* g_reg, double R, double* g);
+
+/* out[0] = sum_i a_i b_i w_i (w null: weights 1), device vectors of length n;
+ * one workgroup, fixed summation order (deterministic).  Used for the norms
+ * of (24) and the inner products of the line search (Algorithm 1). */
+fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b,
+                   const double* w, double* out);
+
 /* Kernel timing (measurement support).  While enabled, every stride-th launch
  * of each kernel class is bracketed by HIP events recorded on the stream the
  * kernel is launched on; fwi_timing_read waits for those events and returns
@@ -168,6 +193,8 @@ fwi_status fwi_timing_read(fwi_plan* plan, int kernel_class, double* mean_ms,
                            int64_t* samples, int64_t* launches);
 
 const char* fwi_status_string(fwi_status s);
+/* Message of the plan's last failed call; with plan = NULL, of the last
+ * failed fwi_plan_create on the calling thread. */
 const char* fwi_last_error(const fwi_plan* plan);
 
 #ifdef __cplusplus

@@ -27,7 +27,14 @@ What it computes, and the passage each part follows:
 * ``matfree``  -- element-by-element application of the same operators for
                   meshes too large to assemble (cross-checked against
                   ``assemble`` on small meshes).
+* ``regularize`` -- Tikhonov (8) and total-variation (9) terms with their
+                  gradients (C.1b)-(C.1e), M~ (C.1a) and the control
+                  problem (18).
+* ``fwi``      -- the reduced-space inversion of Sec. 3.2: L-BFGS search
+                  directions, Armijo backtracking (Algorithm 1), the loop of
+                  Algorithm 2 with the regularization factor rule (24) and the
+                  biased lambda direction (25).
 
-Readings of the paper where it is silent or garbled are listed in the design doc
-and at the functions that use them.
+Readings of the paper where it is silent or garbled are stated at the
+functions that use them.
 """

@@ -6,11 +6,14 @@ hybrid displacement / displacement-stress PML system (6), misfit (7), adjoint
 C ABI declared in ``include/pmlfwi.h``.
 
 ``binding`` is the thin ctypes layer (same names as the C entry points);
-``solver`` holds device buffers in torch tensors and calls the binding.
+``solver`` holds device buffers in torch tensors and calls the binding;
+``autograd`` exposes the misfit as a differentiable function of (lam, mu).
 """
-from .binding import (FWI_FP32, FWI_FP64, FwiError, fwi_adjoint_gradient,  # noqa: F401
-                      fwi_apply_operator, fwi_forward, fwi_last_error, fwi_misfit,
-                      fwi_plan_create, fwi_plan_destroy, fwi_query, fwi_status_string,
-                      fwi_timing_enable, fwi_timing_read, KERNEL_CLASSES,
-                      make_problem)
+from .binding import (FWI_FP32, FWI_FP64, FWI_REG_TIKHONOV, FWI_REG_TV,  # noqa: F401
+                      FwiError, fwi_adjoint_gradient, fwi_apply_operator, fwi_dot,
+                      fwi_forward, fwi_gradient_finalize, fwi_last_error, fwi_material_mass,
+                      fwi_misfit, fwi_plan_create, fwi_plan_destroy, fwi_query,
+                      fwi_regularization, fwi_status_string, fwi_timing_enable,
+                      fwi_timing_read, KERNEL_CLASSES, make_problem)
 from .solver import Solver  # noqa: F401
+from .autograd import MisfitFunction, misfit  # noqa: F401

@@ -63,13 +63,20 @@ _lib.fwi_status_string.argtypes = [ctypes.c_int]
 _lib.fwi_status_string.restype = ctypes.c_char_p
 _lib.fwi_last_error.argtypes = [_P]
 _lib.fwi_last_error.restype = ctypes.c_char_p
+_lib.fwi_regularization.argtypes = [_P, _P, ctypes.c_int, ctypes.c_double, _P, _P, _P]
+_lib.fwi_material_mass.argtypes = [_P, _P, _P]
+_lib.fwi_gradient_finalize.argtypes = [_P, _P, _P, _P, ctypes.c_double, _P]
+_lib.fwi_dot.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
 for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
-           "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read"):
+           "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
            "fwi_status_string", "fwi_last_error")
+FWI_REG_TIKHONOV, FWI_REG_TV = 0, 1
 KERNEL_CLASSES = ("interior", "pml", "nodal", "interior_adj", "pml_adj")
 
 
@@ -80,8 +87,8 @@ class FwiError(RuntimeError):
 def _check(status, plan=None, what=""):
     if status != 0:
         msg = _lib.fwi_status_string(status).decode()
-        if plan:
-            detail = _lib.fwi_last_error(plan).decode()
+        if plan or what == "fwi_plan_create":
+            detail = _lib.fwi_last_error(plan or None).decode()
             if detail:
                 msg += f": {detail}"
         raise FwiError(f"{what} failed ({status}): {msg}")
@@ -160,6 +167,24 @@ def fwi_apply_operator(plan, stream, which, rho, lam, mu, x0, x1, x2, workspace,
     _check(_lib.fwi_apply_operator(plan, _stream(stream), int(which), _ptr(rho), _ptr(lam), _ptr(mu),
                                    _ptr(x0), _ptr(x1), _ptr(x2), _ptr(workspace), _ptr(out)),
            plan, "fwi_apply_operator")
+
+
+def fwi_regularization(plan, stream, kind, eps, field, value, grad):
+    _check(_lib.fwi_regularization(plan, _stream(stream), int(kind), float(eps), _ptr(field), _ptr(value),
+                                   _ptr(grad)), plan, "fwi_regularization")
+
+
+def fwi_material_mass(plan, stream, mdiag):
+    _check(_lib.fwi_material_mass(plan, _stream(stream), _ptr(mdiag)), plan, "fwi_material_mass")
+
+
+def fwi_gradient_finalize(plan, stream, g_mis, g_reg, R, g):
+    _check(_lib.fwi_gradient_finalize(plan, _stream(stream), _ptr(g_mis), _ptr(g_reg), float(R), _ptr(g)),
+           plan, "fwi_gradient_finalize")
+
+
+def fwi_dot(stream, n, a, b, w, out):
+    _check(_lib.fwi_dot(_stream(stream), int(n), _ptr(a), _ptr(b), _ptr(w), _ptr(out)), None, "fwi_dot")
 
 
 def fwi_timing_enable(plan, stride):

@@ -11,8 +11,12 @@
 
 #include "pmlfwi.h"
 #include "kernels.h"
+#include "regularize.h"
 
 using namespace pmlfwi;
+
+// Message of the last failed fwi_plan_create on this thread (no plan to hold it).
+static thread_local std::string g_plan_err;
 
 struct fwi_plan {
   fwi_problem prob;
@@ -701,16 +705,24 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = up((void**)&p->d_tiles_int, p->tiles_int.data(), p->tiles_int.size() * sizeof(Tile));
-  if (e == hipSuccess) e = up((void**)&p->d_tiles_pml, p->tiles_pml.data(), p->tiles_pml.size() * sizeof(Tile));
-  if (e == hipSuccess) e = up((void**)&p->d_src, src_node, prob->nsrc * sizeof(int32_t));
-  if (e == hipSuccess) e = up((void**)&p->d_dir, src_dir, prob->nsrc * 3 * sizeof(double));
-  if (e == hipSuccess) e = up((void**)&p->d_rec, rec_node, prob->nrec * sizeof(int32_t));
-  if (e == hipSuccess) e = up((void**)&p->d_tab, p->tab.data(), p->tab.size() * sizeof(double));
-  if (e == hipSuccess) e = up((void**)&p->d_fo, p->fo.data(), p->fo.size() * sizeof(int));
+  const char* what = "";
+  auto step = [&](const char* name, void** dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) {
+      e = up(dst, src, bytes);
+      what = name;
+    }
+  };
+  step("brick tiles", (void**)&p->d_tiles_int, p->tiles_int.data(), p->tiles_int.size() * sizeof(Tile));
+  step("PML tiles", (void**)&p->d_tiles_pml, p->tiles_pml.data(), p->tiles_pml.size() * sizeof(Tile));
+  step("source nodes", (void**)&p->d_src, src_node, prob->nsrc * sizeof(int32_t));
+  step("source directions", (void**)&p->d_dir, src_dir, prob->nsrc * 3 * sizeof(double));
+  step("receiver nodes", (void**)&p->d_rec, rec_node, prob->nrec * sizeof(int32_t));
+  step("axis tables", (void**)&p->d_tab, p->tab.data(), p->tab.size() * sizeof(double));
+  step("face ordinals", (void**)&p->d_fo, p->fo.data(), p->fo.size() * sizeof(int));
   p->g.tab = p->d_tab;
   p->g.fo = p->d_fo;
   if (e != hipSuccess) {
+    g_plan_err = std::string("fwi_plan_create: upload of the ") + what + ": " + hipGetErrorString(e);
     fwi_plan_destroy(p);
     return FWI_ERR_HIP;
   }
@@ -814,6 +826,45 @@ fwi_status fwi_apply_operator(fwi_plan* p, void* stream, int which, const double
                   [&](auto& r) { return r.apply(which, rho, lam, mu, x0, x1, x2, out); });
 }
 
+fwi_status fwi_regularization(fwi_plan* p, void* stream, int kind, double eps, const double* field,
+                              double* value, double* grad) {
+  if (!p) return FWI_ERR_ARG;
+  if (kind != FWI_REG_TIKHONOV && kind != FWI_REG_TV)
+    return fail(p, FWI_ERR_ARG, "fwi_regularization: kind must be FWI_REG_TIKHONOV or FWI_REG_TV");
+  if (kind == FWI_REG_TV && !(eps > 0)) return fail(p, FWI_ERR_ARG, "fwi_regularization: TV needs eps > 0");
+  if (!field || (!value && !grad)) return fail(p, FWI_ERR_ARG, "fwi_regularization: null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const Geo& G = p->g;
+  const int k = kind == FWI_REG_TIKHONOV ? REG_TN : REG_TV;
+  if (grad) reg_gradient_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, k, eps, field, grad);
+  if (value) reg_value_kernel<<<1, 1024, 0, st>>>(G, k, eps, field, value);
+  HIP_TRY(p, hipGetLastError());
+  return FWI_OK;
+}
+
+fwi_status fwi_material_mass(fwi_plan* p, void* stream, double* mdiag) {
+  if (!p) return FWI_ERR_ARG;
+  if (!mdiag) return fail(p, FWI_ERR_ARG, "fwi_material_mass: null pointer");
+  material_mass_kernel<<<blocks(p->g.n_int, 256), 256, 0, (hipStream_t)stream>>>(p->g, mdiag);
+  HIP_TRY(p, hipGetLastError());
+  return FWI_OK;
+}
+
+fwi_status fwi_gradient_finalize(fwi_plan* p, void* stream, const double* g_mis, const double* g_reg, double R,
+                                 double* g) {
+  if (!p) return FWI_ERR_ARG;
+  if (!g_mis || !g || (R != 0.0 && !g_reg)) return fail(p, FWI_ERR_ARG, "fwi_gradient_finalize: null pointer");
+  gradient_finalize_kernel<<<blocks(p->g.n_int, 256), 256, 0, (hipStream_t)stream>>>(p->g, g_mis, g_reg, R, g);
+  HIP_TRY(p, hipGetLastError());
+  return FWI_OK;
+}
+
+fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b, const double* w, double* out) {
+  if (n < 0 || !out || (n > 0 && (!a || !b))) return FWI_ERR_ARG;
+  dot_kernel<<<1, 1024, 0, (hipStream_t)stream>>>((long long)n, a, b, w, out);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
 const char* fwi_status_string(fwi_status s) {
   switch (s) {
     case FWI_OK: return "ok";
@@ -827,6 +878,6 @@ const char* fwi_status_string(fwi_status s) {
   return "unknown status";
 }
 
-const char* fwi_last_error(const fwi_plan* p) { return p ? p->err.c_str() : "no plan"; }
+const char* fwi_last_error(const fwi_plan* p) { return p ? p->err.c_str() : g_plan_err.c_str(); }
 
 }  // extern "C"

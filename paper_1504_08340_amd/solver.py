@@ -34,6 +34,7 @@ class Solver:
         nbytes = int(self.sizes.workspace_bytes)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         self.trace_shape = (self.nsrc, self.nsteps + 1, self.nrec, 3)
+        self.generation = 0     # bumped by every forward solve (see autograd.py)
 
     def close(self):
         if self.plan is not None:
@@ -58,6 +59,7 @@ class Solver:
     # -- C ABI calls -------------------------------------------------------
     def forward(self, rho, lam, mu, wavelet, traces=None, stream=None):
         traces = self.empty_traces() if traces is None else traces
+        self.generation += 1
         B.fwi_forward(self.plan, stream, rho, lam, mu, wavelet, self.workspace, traces)
         return traces
 

@@ -64,3 +64,19 @@ def test_query_rejects_bad_problems():
         setattr(p, field, val)
         with pytest.raises(binding.FwiError):
             binding.fwi_query(p)
+
+
+def test_checkpoint_spacing_shrinks_the_workspace():
+    """40x40x20 m mesh, 4 sources, 2000 steps, FP64: keeping a full state every k
+    steps (and one segment of stage displacements) instead of every stage."""
+    from paper_1504_08340_amd import binding
+    wl = W.config2(nsteps=2000)
+
+    def ws(k):
+        return binding.fwi_query(binding.make_problem(wl.prob, 4, wl.nrec, 0, k)).workspace_bytes
+
+    full = ws(0)
+    sizes = {k: ws(k) for k in (10, 50, 200)}
+    print({k: f"{v / 2**30:.1f} GiB" for k, v in sizes.items()}, f"k=0: {full / 2**30:.1f} GiB")
+    assert all(v * 3 < full for v in sizes.values())
+    assert sizes[50] < sizes[10] and sizes[50] < sizes[200]
