@@ -20,6 +20,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
         "or `python paper_1504_08340_amd/_build.py` (hipcc, gfx950)")
 
+# torch ships its own HIP runtime; it must be the one in the process before
+# the library is loaded, so that the library's HIP calls and torch's device
+# memory and streams share a single runtime (loading the library first pulls
+# in a second runtime, which then sees no device).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 
