@@ -10,7 +10,8 @@ One bench step = one pass of the whole hot path on that batch: forward solve
 (6) with traces, misfit (7), adjoint solve (15) and Lame-parameter gradient
 (18).  value = n_state * nsteps * nsrc / (seconds per bench step).
 
-Usage: python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+Usage: python bench.py [--steps K] [--warmup W]
+                       [--precision fp32|fp64|fp32-mfma|fp32-bf16x3]
                        [--ckpt k] [--nsteps N] [--no-cpu-baseline]
                        [--copy-probe-mib MiB]
 
@@ -35,6 +36,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+MFMA_PEAK_TFLOPS = {"fp32-mfma": 157.3, "fp32-bf16x3": 2500.0}   # dense, published
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32-mfma": 2, "fp32-bf16x3": 3}
+# Matrix-core work of one interior workgroup (a 4x2x2 brick tile, one source):
+# G = B U with B 81x27 padded to 96 rows, U 27x48; R = B^T S with 27 rows
+# padded to 32, K = 81.  FP32 16x16x4 MFMA: 18 tiles x 7 steps + 6 tiles x 21
+# steps; split BF16 16x16x16: 18 x 2 + 6 x 6 steps, 3 products each.
+MFMA_FLOPS_PER_TILE = {"fp32-mfma": (18 * 7 + 6 * 21) * 2 * 16 * 16 * 4,
+                       "fp32-bf16x3": (18 * 2 + 6 * 6) * 3 * 2 * 16 * 16 * 16}
+USEFUL_FLOPS_PER_TILE = 2 * (2 * 81 * 27 * 48)
 CSRC = os.path.join(ROOT, "paper_1504_08340_amd", "csrc")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic__kernels__cfg40x40x20_4src_fp32.md")
 
@@ -122,7 +132,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--precision", choices=tuple(PRECISIONS), default="fp32")
     ap.add_argument("--ckpt", type=int, default=0)
     ap.add_argument("--nsteps", type=int, default=2000)
     ap.add_argument("--timing-stride", type=int, default=7)   # odd: samples every RK4 stage mode
@@ -142,8 +152,8 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    prec = P.FWI_FP32 if args.precision == "fp32" else P.FWI_FP64
-    es = 4 if prec == P.FWI_FP32 else 8
+    prec = PRECISIONS[args.precision]
+    es = 8 if prec == 0 else 4
     wl = W.config2(nsteps=args.nsteps)
     prob = wl.prob
     t0 = time.time()
@@ -210,6 +220,16 @@ def main():
         print("# cpu baseline (oracle sample) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl, n_state)
 
+    mfma = None
+    if args.precision in MFMA_PEAK_TFLOPS and "interior" in kstats:
+        ex, ey, ez = prob.ne_int
+        tiles = -(-ex // 4) * -(-ey // 2) * -(-ez // 2)
+        t = kstats["interior"]["mean_ms"] * 1e-3
+        executed = tiles * wl.nsrc * MFMA_FLOPS_PER_TILE[args.precision] / t / 1e12
+        mfma = {"kernel": "interior", "executed_tflops": executed, "peak": MFMA_PEAK_TFLOPS[args.precision],
+                "unit": "TFLOP/s", "frac": executed / MFMA_PEAK_TFLOPS[args.precision],
+                "useful_tflops": tiles * wl.nsrc * USEFUL_FLOPS_PER_TILE / t / 1e12,
+                "mean_launch_us": kstats["interior"]["mean_ms"] * 1e3}
     line = {
         "metric": "RK4 DOF-steps/s fwd+adj",
         "value": value,
@@ -221,7 +241,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == P.FWI_FP32 else "f64",
+        "dtype": "f64" if prec == 0 else "f32",
         "data": "synthetic",
         "config": {
             "workload": "40x40x20 m interior, 1 m Q2 bricks, 5-brick PML (62,500 bricks), "
@@ -239,6 +259,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if mfma is not None:
+        line["mfma"] = mfma
     print(json.dumps(line), flush=True)
 
 

@@ -9,7 +9,8 @@ C ABI declared in ``include/pmlfwi.h``.
 ``solver`` holds device buffers in torch tensors and calls the binding;
 ``autograd`` exposes the misfit as a differentiable function of (lam, mu).
 """
-from .binding import (FWI_FP32, FWI_FP64, FWI_REG_TIKHONOV, FWI_REG_TV,  # noqa: F401
+from .binding import (FWI_FP32, FWI_FP32_BF16X3, FWI_FP32_MFMA, FWI_FP64,  # noqa: F401
+                      FWI_REG_TIKHONOV, FWI_REG_TV,
                       FwiError, fwi_adjoint_gradient, fwi_apply_operator, fwi_dot,
                       fwi_forward, fwi_gradient_finalize, fwi_last_error, fwi_material_mass,
                       fwi_misfit, fwi_plan_create, fwi_plan_destroy, fwi_query,

@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("PMLFWI_LIB") or os.path.join(HERE, "libpmlfwi.so")
 
-FWI_FP64, FWI_FP32 = 0, 1
+FWI_FP64, FWI_FP32, FWI_FP32_MFMA, FWI_FP32_BF16X3 = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

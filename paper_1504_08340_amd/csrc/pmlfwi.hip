@@ -10,8 +10,11 @@
 #include <vector>
 
 #include "pmlfwi.h"
+#include <type_traits>
+
 #include "kernels.h"
 #include "regularize.h"
+#include "mfma.h"
 
 using namespace pmlfwi;
 
@@ -224,7 +227,7 @@ Layout layout(const fwi_problem& P, const Geo& g) {
   const int nface[3] = {count_faces(P, g, 0), count_faces(P, g, 1), count_faces(P, g, 2)};
   L.part = part_layout(g, nface, 9, true);
   L.gpart = part_layout(g, nface, 2, false);
-  L.es = P.precision == FWI_FP32 ? 4 : 8;
+  L.es = P.precision == FWI_FP64 ? 8 : 4;
   L.reg_elems = (size_t)U_NCOMP * g.sn + (size_t)P_NCOMP * g.sp;
   L.res_elems = 3 * (size_t)g.sn + 6 * (size_t)g.sp;
   L.stage_elems = (size_t)P.nsrc * 3 * g.si;
@@ -252,7 +255,7 @@ fwi_status validate(const fwi_problem* P) {
   if (P->npml_side < 1 || P->npml_bottom < 1) return FWI_ERR_SHAPE;
   if (!(P->h > 0) || !(P->dt > 0) || P->nsteps < 1) return FWI_ERR_ARG;
   if (P->nsrc < 1 || P->nrec < 0 || P->pml_m < 0 || P->ckpt_every < 0) return FWI_ERR_ARG;
-  if (P->precision != FWI_FP64 && P->precision != FWI_FP32) return FWI_ERR_ARG;
+  if (P->precision < FWI_FP64 || P->precision > FWI_FP32_BF16X3) return FWI_ERR_ARG;
   const double nx = 2.0 * (P->ne_int[0] + 2.0 * P->npml_side) + 1;
   const double ny = 2.0 * (P->ne_int[1] + 2.0 * P->npml_side) + 1;
   const double nz = 2.0 * (P->ne_int[2] + P->npml_bottom) + 1;
@@ -453,6 +456,24 @@ struct Run {
     return FWI_OK;
   }
 
+  // Interior operator on the matrix cores for the FP32-state precisions that
+  // ask for it; false when the scalar kernel is to be used.
+  bool mfma_interior(const R* Y, int nt, unsigned gx) {
+    if constexpr (std::is_same<R, float>::value) {
+      const int pr = p->prob.precision;
+      if (pr != FWI_FP32_MFMA && pr != FWI_FP32_BF16X3) return false;
+      const dim3 grid(gx, p->nsrc);
+      if (pr == FWI_FP32_MFMA)
+        interior_mfma_kernel<MFMA_F32, TX, TY, TZ><<<grid, 256, 0, st>>>(
+            g(), p->d_tiles_int, nt, Y, (long long)L.reg_elems, lam(), mu(), res(), L.part);
+      else
+        interior_mfma_kernel<MFMA_BF16X3, TX, TY, TZ><<<grid, 256, 0, st>>>(
+            g(), p->d_tiles_int, nt, Y, (long long)L.reg_elems, lam(), mu(), res(), L.part);
+      return true;
+    }
+    return false;
+  }
+
   fwi_status elements(bool adj, const R* Y, const R* fwd, double gw) {
     const Geo& G = g();
     const long long reg = (long long)L.reg_elems;
@@ -464,7 +485,7 @@ struct Run {
       if (fwd)
         interior_element_kernel<R, TX, TY, TZ, true, true><<<dim3(gx, 1), ETHREADS, 0, st>>>(
             G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, fwd, 3LL * G.si, gw, gacc(), L.gpart);
-      else
+      else if (!mfma_interior(Y, nt, gx))
         interior_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<dim3(gx, SRCLOOP ? 1 : ns), ETHREADS, 0, st>>>(
             G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, nullptr, 0, 0.0, nullptr, L.gpart);
     }
@@ -642,7 +663,7 @@ struct Run {
 template <typename F>
 fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f) {
   Layout L = layout(p->prob, p->g);
-  if (p->prob.precision == FWI_FP32) {
+  if (p->prob.precision != FWI_FP64) {
     Run<float> r{p, st, L, (char*)ws};
     return f(r);
   }
