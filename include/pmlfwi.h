@@ -184,6 +184,44 @@ fwi_status fwi_gradient_finalize(fwi_plan* plan, void* stream, const double* g_m
 fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b,
                    const double* w, double* out);
 
+/* ---- Learned warm start: a small 3D convolutional network (FP32, device
+ * arrays, NCDHW: batch, channel, then three spatial axes, the last fastest).
+ * Cubic kernels of size K = 1 or 3 with zero padding K/2 and per-axis
+ * strides; output extent (n + 2 (K/2) - K) / s + 1 per axis.  All
+ * reductions run in a fixed order (deterministic). */
+typedef struct {
+  int32_t N, Ci, D, H, W;  /* input batch, channels, extents */
+  int32_t Co, K;           /* output channels, kernel size */
+  int32_t sd, sh, sw;      /* strides */
+} fwi_conv_shape;
+
+/* y = act(b + w * x); w [Co][Ci][K][K][K], b [Co] (may be null); relu != 0
+ * applies max(0, .). */
+fwi_status fwi_conv3d_forward(void* stream, const fwi_conv_shape* shape, const float* x,
+                              const float* w, const float* b, int relu, float* y);
+/* Gradients from dy = dL/dy: dx (may be null), dw, db (may be null); with
+ * relu, y is the activated forward output (the mask is y > 0). */
+fwi_status fwi_conv3d_backward(void* stream, const fwi_conv_shape* shape, const float* x,
+                               const float* w, const float* y, const float* dy, int relu,
+                               float* dx, float* dw, float* db);
+/* loss[0] = 1/(2n) sum (y - t)^2, grad = (y - t)/n; either may be null. */
+fwi_status fwi_mse(void* stream, int64_t n, const float* y, const float* t, float* loss,
+                   float* grad);
+/* One Adam step (bias-corrected, step >= 1) on param with moments m, v. */
+fwi_status fwi_adam(void* stream, int64_t n, float* param, const float* grad, float* m,
+                    float* v, float lr, float beta1, float beta2, float eps, int step);
+/* Network input from traces [nsrc][nsteps+1][nrec][3] (FP64): component comp
+ * at receivers rec_idx[hw] and steps t0 + t*tstride (t < T; zero past nsteps),
+ * times scale -> out [nsrc][T][hw] (FP32). */
+fwi_status fwi_trace_features(void* stream, const double* traces, int nsrc, int nsteps,
+                              int nrec, const int32_t* rec_idx, int hw, int T, int t0,
+                              int tstride, int comp, float scale, float* out);
+/* Coarse relative perturbation c [gz][gy][gx] on cell centres of a regular
+ * grid over the closed interior box (z index 0 at the surface) -> nodal
+ * field out = base * (1 + trilinear(c)), n_int_nodes, clamped at the edges. */
+fwi_status fwi_grid_to_nodes(fwi_plan* plan, void* stream, const float* coarse, int gx,
+                             int gy, int gz, const double* base, double* out);
+
 /* Kernel timing (measurement support).  While enabled, every stride-th launch
  * of each kernel class is bracketed by HIP events recorded on the stream the
  * kernel is launched on; fwi_timing_read waits for those events and returns

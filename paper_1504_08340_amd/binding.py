@@ -73,15 +73,33 @@ _lib.fwi_regularization.argtypes = [_P, _P, ctypes.c_int, ctypes.c_double, _P, _
 _lib.fwi_material_mass.argtypes = [_P, _P, _P]
 _lib.fwi_gradient_finalize.argtypes = [_P, _P, _P, _P, ctypes.c_double, _P]
 _lib.fwi_dot.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
+
+
+class fwi_conv_shape(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("N", "Ci", "D", "H", "W", "Co", "K", "sd", "sh", "sw")]
+
+
+_CS = ctypes.POINTER(fwi_conv_shape)
+_F = ctypes.c_float
+_lib.fwi_conv3d_forward.argtypes = [_P, _CS, _P, _P, _P, ctypes.c_int, _P]
+_lib.fwi_conv3d_backward.argtypes = [_P, _CS, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P]
+_lib.fwi_mse.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
+_lib.fwi_adam.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _F, _F, _F, _F, ctypes.c_int]
+_lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _P]
+_lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]
 for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
-           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot"):
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
+           "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
+           "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
-           "fwi_status_string", "fwi_last_error")
+           "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
+           "fwi_grid_to_nodes", "fwi_status_string", "fwi_last_error")
 FWI_REG_TIKHONOV, FWI_REG_TV = 0, 1
 KERNEL_CLASSES = ("interior", "pml", "nodal", "interior_adj", "pml_adj")
 
@@ -191,6 +209,43 @@ def fwi_gradient_finalize(plan, stream, g_mis, g_reg, R, g):
 
 def fwi_dot(stream, n, a, b, w, out):
     _check(_lib.fwi_dot(_stream(stream), int(n), _ptr(a), _ptr(b), _ptr(w), _ptr(out)), None, "fwi_dot")
+
+
+def conv_shape(N, Ci, D, H, W, Co, K, strides):
+    s = fwi_conv_shape()
+    s.N, s.Ci, s.D, s.H, s.W, s.Co, s.K = N, Ci, D, H, W, Co, K
+    s.sd, s.sh, s.sw = strides
+    return s
+
+
+def fwi_conv3d_forward(stream, shape, x, w, b, relu, y):
+    _check(_lib.fwi_conv3d_forward(_stream(stream), ctypes.byref(shape), _ptr(x), _ptr(w), _ptr(b), int(relu),
+                                   _ptr(y)), None, "fwi_conv3d_forward")
+
+
+def fwi_conv3d_backward(stream, shape, x, w, y, dy, relu, dx, dw, db):
+    _check(_lib.fwi_conv3d_backward(_stream(stream), ctypes.byref(shape), _ptr(x), _ptr(w), _ptr(y), _ptr(dy),
+                                    int(relu), _ptr(dx), _ptr(dw), _ptr(db)), None, "fwi_conv3d_backward")
+
+
+def fwi_mse(stream, n, y, t, loss, grad):
+    _check(_lib.fwi_mse(_stream(stream), int(n), _ptr(y), _ptr(t), _ptr(loss), _ptr(grad)), None, "fwi_mse")
+
+
+def fwi_adam(stream, n, param, grad, m, v, lr, beta1, beta2, eps, step):
+    _check(_lib.fwi_adam(_stream(stream), int(n), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), float(lr),
+                         float(beta1), float(beta2), float(eps), int(step)), None, "fwi_adam")
+
+
+def fwi_trace_features(stream, traces, nsrc, nsteps, nrec, rec_idx, hw, T, t0, tstride, comp, scale, out):
+    _check(_lib.fwi_trace_features(_stream(stream), _ptr(traces), int(nsrc), int(nsteps), int(nrec), _ptr(rec_idx),
+                                   int(hw), int(T), int(t0), int(tstride), int(comp), float(scale), _ptr(out)),
+           None, "fwi_trace_features")
+
+
+def fwi_grid_to_nodes(plan, stream, coarse, gx, gy, gz, base, out):
+    _check(_lib.fwi_grid_to_nodes(plan, _stream(stream), _ptr(coarse), int(gx), int(gy), int(gz), _ptr(base),
+                                  _ptr(out)), plan, "fwi_grid_to_nodes")
 
 
 def fwi_timing_enable(plan, stride):

@@ -15,6 +15,7 @@
 #include "kernels.h"
 #include "regularize.h"
 #include "mfma.h"
+#include "convnet.h"
 
 using namespace pmlfwi;
 
@@ -884,6 +885,75 @@ fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b, co
   if (n < 0 || !out || (n > 0 && (!a || !b))) return FWI_ERR_ARG;
   dot_kernel<<<1, 1024, 0, (hipStream_t)stream>>>((long long)n, a, b, w, out);
   return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+static bool conv_shape(const fwi_conv_shape* s, ConvShape& c) {
+  if (!s || s->N < 1 || s->Ci < 1 || s->D < 1 || s->H < 1 || s->W < 1 || s->Co < 1) return false;
+  if ((s->K != 1 && s->K != 3) || s->sd < 1 || s->sh < 1 || s->sw < 1) return false;
+  c = ConvShape{s->N, s->Ci, s->D, s->H, s->W, s->Co, s->K, s->sd, s->sh, s->sw,
+                conv_out(s->D, s->K, s->sd), conv_out(s->H, s->K, s->sh), conv_out(s->W, s->K, s->sw)};
+  return c.Do >= 1 && c.Ho >= 1 && c.Wo >= 1;
+}
+
+fwi_status fwi_conv3d_forward(void* stream, const fwi_conv_shape* shape, const float* x, const float* w,
+                              const float* b, int relu, float* y) {
+  ConvShape c;
+  if (!conv_shape(shape, c) || !x || !w || !y) return FWI_ERR_ARG;
+  const long long n = (long long)c.N * c.Co * c.Do * c.Ho * c.Wo;
+  conv3d_forward_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(c, x, w, b, relu, y);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_conv3d_backward(void* stream, const fwi_conv_shape* shape, const float* x, const float* w,
+                               const float* y, const float* dy, int relu, float* dx, float* dw, float* db) {
+  ConvShape c;
+  if (!conv_shape(shape, c) || !x || !w || !dy || (relu && !y) || !dw) return FWI_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  if (dx) {
+    const long long n = (long long)c.N * c.Ci * c.D * c.H * c.W;
+    conv3d_backward_data_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(c, dy, y, relu, w, dx);
+  }
+  conv3d_backward_weight_kernel<<<(unsigned)(c.Co * c.Ci * c.K * c.K * c.K), 256, 0, st>>>(c, dy, y, relu, x, dw);
+  if (db) conv3d_backward_bias_kernel<<<(unsigned)c.Co, 256, 0, st>>>(c, dy, y, relu, db);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_mse(void* stream, int64_t n, const float* y, const float* t, float* loss, float* grad) {
+  if (n < 1 || !y || !t || (!loss && !grad)) return FWI_ERR_ARG;
+  mse_kernel<<<1, 1024, 0, (hipStream_t)stream>>>((long long)n, y, t, loss, grad);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_adam(void* stream, int64_t n, float* param, const float* grad, float* m, float* v, float lr,
+                    float beta1, float beta2, float eps, int step) {
+  if (n < 1 || !param || !grad || !m || !v || step < 1) return FWI_ERR_ARG;
+  adam_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>((long long)n, param, grad, m, v, lr,
+                                                                            beta1, beta2, eps, step);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_trace_features(void* stream, const double* traces, int nsrc, int nsteps, int nrec,
+                              const int32_t* rec_idx, int hw, int T, int t0, int tstride, int comp, float scale,
+                              float* out) {
+  if (!traces || !rec_idx || !out || nsrc < 1 || nsteps < 1 || nrec < 1 || hw < 1 || T < 1 || t0 < 0 ||
+      tstride < 1 || comp < 0 || comp > 2)
+    return FWI_ERR_ARG;
+  const long long n = (long long)nsrc * T * hw;
+  trace_features_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+      traces, nsrc, nsteps, nrec, rec_idx, hw, T, t0, tstride, comp, scale, out);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_grid_to_nodes(fwi_plan* p, void* stream, const float* coarse, int gx, int gy, int gz,
+                             const double* base, double* out) {
+  if (!p) return FWI_ERR_ARG;
+  if (!coarse || !base || !out || gx < 1 || gy < 1 || gz < 1)
+    return fail(p, FWI_ERR_ARG, "fwi_grid_to_nodes: bad argument");
+  const Geo& G = p->g;
+  grid_to_nodes_kernel<<<blocks(G.n_int, 256), 256, 0, (hipStream_t)stream>>>(coarse, gx, gy, gz, G.NIX, G.NIY,
+                                                                               G.NIZ, base, out);
+  HIP_TRY(p, hipGetLastError());
+  return FWI_OK;
 }
 
 const char* fwi_status_string(fwi_status s) {

@@ -16,7 +16,7 @@ LIB = os.path.join(ROOT, "paper_1504_08340_amd", "libpmlfwi.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fwi_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(fwi_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")

@@ -334,3 +334,31 @@ def config3(nsteps=1500, fc=4.0):
     rec = surface_receivers(prob)
     return Workload("cfg3", prob, rho, lam, mu, wav, src, dirs, rec,
                     lam_t, mu_t)
+
+
+def layered_profile_vs(prob, seed):
+    """Seeded random profile on the closed interior, shaped like the paper's
+    layered hosts: three layers (interfaces at 3-7 m and 9-13 m depth, vs
+    100-150 / 170-230 / 250-300 m/s), with probability 0.6 a box inclusion
+    (3-5 m edges, 2-8 m deep, vs x0.7-1.3) and a smooth +-5 % random field;
+    vs clipped to [80, 300] m/s."""
+    rng = np.random.default_rng(seed)
+    gx, gy, gz = _interior_grid(prob)
+    d = -gz
+    d1, d2 = rng.uniform(3.0, 7.0), rng.uniform(9.0, 13.0)
+    v1, v2, v3 = rng.uniform(100, 150), rng.uniform(170, 230), rng.uniform(250, 300)
+    vs = np.where(d <= d1, v1, np.where(d <= d2, v2, v3))
+    if rng.uniform() < 0.6:
+        cx, cy, cd = rng.uniform(-10, 10), rng.uniform(-10, 10), rng.uniform(2.0, 8.0)
+        sx, sy, sz = rng.uniform(3.0, 5.0, 3)
+        inside = (np.abs(gx - cx) <= sx / 2) & (np.abs(gy - cy) <= sy / 2) & (np.abs(d - cd) <= sz / 2)
+        vs = np.where(inside, vs * rng.uniform(0.7, 1.3), vs)
+    vs = vs * (1.0 + 0.2 * random_field(prob, seed + 1000, corr_len=6.0, amp=0.25))
+    return np.clip(vs, 80.0, 300.0)
+
+
+def with_model(wl, vs, rho=2000.0):
+    """The workload wl with its target model replaced by the profile vs."""
+    lam_t, mu_t = _model_from_vs(np.full(vs.shape, rho), vs)
+    return Workload(wl.name, wl.prob, wl.rho, wl.lam, wl.mu, wl.wavelet, wl.src_node, wl.src_dir,
+                    wl.rec_node, lam_t, mu_t)
