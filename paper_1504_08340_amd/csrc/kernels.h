@@ -30,6 +30,12 @@
 #pragma once
 #include "geometry.h"
 
+// Threads of an element-kernel workgroup (the kernels loop over the tile's
+// nodes and points in strides of the workgroup size).
+#ifndef PMLFWI_ETHREADS
+#define PMLFWI_ETHREADS 256
+#endif
+
 namespace pmlfwi {
 
 enum { P_X0U = 0, P_X0S = 3, P_X1S = 9, P_X2S = 15, P_NCOMP = 21, U_NCOMP = 6 };
@@ -142,7 +148,7 @@ __device__ __forceinline__ void atomic_add(R* p, R v) {
 // summed over sources and added to FP64 accumulators (gacc: [8][2][n_nodes],
 // slot c indexed like the partial arrays).
 template <typename R, int TX, int TY, int TZ, bool GRAD, bool SRCLOOP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(PMLFWI_ETHREADS)
 interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
                         const R* __restrict__ Ybase, long long ystride, const R* __restrict__ lam,
                         const R* __restrict__ mu, R* __restrict__ rbase, Part PT,
@@ -325,7 +331,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
 //            Z_k = Le_kk T2 + Lp_kk T1 + Lw_kk T0 (symmetric stress-like fields)
 //   S-rows:  r_S += int T~_ab (H_ab + H_ba)  (a != b),  H_aa  (a = b).
 template <typename R, int TX, int TY, int TZ, bool ADJ, bool SRCLOOP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(PMLFWI_ETHREADS)
 pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
                    const R* __restrict__ Ybase, long long ystride, const R* __restrict__ lam,
                    const R* __restrict__ mu, R* __restrict__ rbase, Part PT) {

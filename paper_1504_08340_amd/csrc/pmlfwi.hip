@@ -87,7 +87,7 @@ namespace {
 #endif
 constexpr int TX = PMLFWI_TX, TY = PMLFWI_TY, TZ = PMLFWI_TZ;
 constexpr bool SRCLOOP = PMLFWI_SRCLOOP;
-constexpr int ETHREADS = 256;           // threads per element workgroup
+constexpr int ETHREADS = PMLFWI_ETHREADS;   // threads per element workgroup
 
 fwi_status fail(fwi_plan* p, fwi_status s, const std::string& msg) {
   if (p) p->err = msg;
