@@ -224,17 +224,17 @@ __global__ void grid_to_nodes_kernel(const float* __restrict__ c, int Gx, int Gy
     k0 = min((int)u, G - 2 >= 0 ? G - 2 : 0);
     f = G > 1 ? u - (float)k0 : 0.0f;
   };
-  int x0, y0, z0;
+  int cx0, cy0, cz0;
   float fx, fy, fz;
-  coord(jx, NIX, Gx, x0, fx);
-  coord(jy, NIY, Gy, y0, fy);
-  coord(NIZ - 1 - jz, NIZ, Gz, z0, fz);          // depth index from the top
-  const int x1 = min(x0 + 1, Gx - 1), y1 = min(y0 + 1, Gy - 1), z1 = min(z0 + 1, Gz - 1);
+  coord(jx, NIX, Gx, cx0, fx);
+  coord(jy, NIY, Gy, cy0, fy);
+  coord(NIZ - 1 - jz, NIZ, Gz, cz0, fz);          // depth index from the top
+  const int cx1 = min(cx0 + 1, Gx - 1), cy1 = min(cy0 + 1, Gy - 1), cz1 = min(cz0 + 1, Gz - 1);
   auto at = [&](int z, int y, int x) { return c[((long long)z * Gy + y) * Gx + x]; };
-  const float v = (1 - fz) * ((1 - fy) * ((1 - fx) * at(z0, y0, x0) + fx * at(z0, y0, x1)) +
-                              fy * ((1 - fx) * at(z0, y1, x0) + fx * at(z0, y1, x1))) +
-                  fz * ((1 - fy) * ((1 - fx) * at(z1, y0, x0) + fx * at(z1, y0, x1)) +
-                        fy * ((1 - fx) * at(z1, y1, x0) + fx * at(z1, y1, x1)));
+  const float v = (1 - fz) * ((1 - fy) * ((1 - fx) * at(cz0, cy0, cx0) + fx * at(cz0, cy0, cx1)) +
+                              fy * ((1 - fx) * at(cz0, cy1, cx0) + fx * at(cz0, cy1, cx1))) +
+                  fz * ((1 - fy) * ((1 - fx) * at(cz1, cy0, cx0) + fx * at(cz1, cy0, cx1)) +
+                        fy * ((1 - fx) * at(cz1, cy1, cx0) + fx * at(cz1, cy1, cx1)));
   out[j] = base[j] * (1.0 + (double)v);
 }
 

@@ -44,6 +44,10 @@ struct fwi_plan {
   long long launches[FWI_K_NCLASS] = {};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[FWI_K_NCLASS];
   size_t ev_used[FWI_K_NCLASS] = {};
+  // second stream for the interior bricks, which run beside the PML bricks
+  // (fork and join through events on the caller's stream)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -81,6 +85,9 @@ namespace {
 #define PMLFWI_TX 4
 #define PMLFWI_TY 2
 #define PMLFWI_TZ 2
+#endif
+#ifndef PMLFWI_CONCURRENT
+#define PMLFWI_CONCURRENT 1
 #endif
 #ifndef PMLFWI_SRCLOOP
 #define PMLFWI_SRCLOOP false
@@ -459,7 +466,7 @@ struct Run {
 
   // Interior operator on the matrix cores for the FP32-state precisions that
   // ask for it; false when the scalar kernel is to be used.
-  bool mfma_interior(const R* Y, int nt, unsigned gx) {
+  bool mfma_interior(const R* Y, int nt, unsigned gx, hipStream_t st) {
     if constexpr (std::is_same<R, float>::value) {
       const int pr = p->prob.precision;
       if (pr != FWI_FP32_MFMA && pr != FWI_FP32_BF16X3) return false;
@@ -475,21 +482,37 @@ struct Run {
     return false;
   }
 
+  // The interior and PML bricks write disjoint partial-array entries, so the
+  // two launches may run at the same time: the interior one goes to the plan's
+  // second stream when both lists are non-empty.
   fwi_status elements(bool adj, const R* Y, const R* fwd, double gw) {
     const Geo& G = g();
     const long long reg = (long long)L.reg_elems;
     const int ns = p->nsrc;
+    hipStream_t si = st;
+    const bool fork = PMLFWI_CONCURRENT && !p->tiles_int.empty() && !p->tiles_pml.empty();
+    if (fork) {
+      if (!p->side) {
+        HIP_TRY(p, hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+        HIP_TRY(p, hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+        HIP_TRY(p, hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
+      }
+      HIP_TRY(p, hipEventRecord(p->fork_ev, st));
+      HIP_TRY(p, hipStreamWaitEvent(p->side, p->fork_ev, 0));
+      si = p->side;
+    }
     if (!p->tiles_int.empty()) {
       const int nt = (int)p->tiles_int.size();
       const unsigned gx = 8u * (unsigned)((nt + 7) / 8);
-      TimedLaunch tl(p, fwd ? FWI_K_INTERIOR_ADJ : FWI_K_INTERIOR, st);
+      TimedLaunch tl(p, fwd ? FWI_K_INTERIOR_ADJ : FWI_K_INTERIOR, si);
       if (fwd)
-        interior_element_kernel<R, TX, TY, TZ, true, true><<<dim3(gx, 1), ETHREADS, 0, st>>>(
+        interior_element_kernel<R, TX, TY, TZ, true, true><<<dim3(gx, 1), ETHREADS, 0, si>>>(
             G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, fwd, 3LL * G.si, gw, gacc(), L.gpart);
-      else if (!mfma_interior(Y, nt, gx))
-        interior_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<dim3(gx, SRCLOOP ? 1 : ns), ETHREADS, 0, st>>>(
+      else if (!mfma_interior(Y, nt, gx, si))
+        interior_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<dim3(gx, SRCLOOP ? 1 : ns), ETHREADS, 0, si>>>(
             G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, nullptr, 0, 0.0, nullptr, L.gpart);
     }
+    if (fork) HIP_TRY(p, hipEventRecord(p->join_ev, si));
     if (!p->tiles_pml.empty()) {
       const int nt = (int)p->tiles_pml.size();
       const dim3 grid(8u * (unsigned)((nt + 7) / 8), SRCLOOP ? 1 : ns);
@@ -501,6 +524,7 @@ struct Run {
         pml_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<grid, ETHREADS, 0, st>>>(G, p->d_tiles_pml, nt, ns, Y, reg,
                                                                                      lam(), mu(), res(), L.part);
     }
+    if (fork) HIP_TRY(p, hipStreamWaitEvent(st, p->join_ev, 0));
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
@@ -785,6 +809,10 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
+  if (p->side) (void)hipStreamSynchronize(p->side);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->join_ev) (void)hipEventDestroy(p->join_ev);
+  if (p->side) (void)hipStreamDestroy(p->side);
   (void)hipFree(p->d_tiles_int);
   (void)hipFree(p->d_tiles_pml);
   (void)hipFree(p->d_src);
