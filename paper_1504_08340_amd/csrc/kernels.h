@@ -330,6 +330,229 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
 //   u-rows:  r_u += int grad w~ : T',  T'_ik = -(mu (1+d_ik) Z_k,ik + lam d_ik tr Z_i),
 //            Z_k = Le_kk T2 + Lp_kk T1 + Lw_kk T0 (symmetric stress-like fields)
 //   S-rows:  r_S += int T~_ab (H_ab + H_ba)  (a != b),  H_aa  (a = b).
+//
+// A workgroup works in three phases per source: (1) every box node's register
+// values become the nodal fields W and T in LDS, (2) every LGL point of every
+// brick forms Q from the gradients of W, (3) every box node sums its u-rows
+// (factorized over the axes, T being nodal) and S-rows and stores them.
+
+template <typename R>
+struct PmlNode {          // register values of one box node for one source
+  R u1[3], u2[3], u0[3], s0[6], s1[6], s2[6];
+};
+
+template <typename R>
+__device__ __forceinline__ void pml_load_node(const R* __restrict__ Y, size_t nn, size_t np, size_t gnode,
+                                              size_t gp, bool hist, PmlNode<R>& v) {
+  const R* P = Y + 6 * nn;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    v.u1[d] = Y[d * nn + gnode];
+    v.u2[d] = Y[(3 + d) * nn + gnode];
+    v.u0[d] = hist ? P[(P_X0U + d) * np + gp] : R(0);
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    v.s1[c] = P[(P_X1S + c) * np + gp];
+    v.s2[c] = P[(P_X2S + c) * np + gp];
+    v.s0[c] = hist ? P[(P_X0S + c) * np + gp] : R(0);
+  }
+}
+
+// Phase 1 for one node: W and T from its register values.
+template <typename R, bool ADJ, int NB>
+__device__ __forceinline__ void pml_node_fields(const PmlNode<R>& v, const R Le[3], const R Lp[3], const R Lw[3],
+                                                R la, R m, int n, R (&sW)[9][NB], R (&sT)[9][NB]) {
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) sW[3 * kk + ii][n] = Le[kk] * v.u2[ii] + Lp[kk] * v.u1[ii] + Lw[kk] * v.u0[ii];
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        const int c = vidx(ii, kk);
+        sT[3 * ii + kk][n] = Le[kk] * v.s2[c] + Lp[kk] * v.s1[c] + Lw[kk] * v.s0[c];
+      }
+  } else {
+    const R t2 = v.s2[0] + v.s2[1] + v.s2[2], t1 = v.s1[0] + v.s1[1] + v.s1[2], t0 = v.s0[0] + v.s0[1] + v.s0[2];
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        const int c = vidx(ii, kk);
+        const R z = Le[kk] * v.s2[c] + Lp[kk] * v.s1[c] + Lw[kk] * v.s0[c];
+        R val = (ii == kk ? R(2) : R(1)) * m * z;
+        if (ii == kk) val += la * (Le[ii] * t2 + Lp[ii] * t1 + Lw[ii] * t0);
+        sT[3 * ii + kk][n] = -val;
+      }
+  }
+}
+
+// Q (6 values) at LGL point q of the tile's bricks; false for points of bricks
+// outside a ragged tile.
+template <typename R, int TX, int TY, int TZ, bool ADJ>
+__device__ __forceinline__ bool pml_point_value(const Geo& g, int cx, int cy, int cz, int q,
+                                                const R* __restrict__ sW,
+                                                const R (&sLam)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
+                                                const R (&sMu)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
+                                                R Q[6]) {
+  constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, NB = BX * BY * (2 * TZ + 1);
+  const R s2h = R(2.0 / g.h);
+  const int pt = q % 27, e = q / 27;
+  const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
+  if (ea >= cx || eb >= cy || ec >= cz) return false;
+  const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
+  const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
+  R H[3][3];
+#pragma unroll
+  for (int ii = 0; ii < 3; ++ii) {
+    R hx = 0, hy = 0, hz = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      hx += R(dlgl(qa, a)) * sW[(0 + ii) * NB + (2 * ea + a) + BX * (ly + BY * lz)];
+      hy += R(dlgl(qb, a)) * sW[(3 + ii) * NB + lx + BX * ((2 * eb + a) + BY * lz)];
+      hz += R(dlgl(qc, a)) * sW[(6 + ii) * NB + lx + BX * (ly + BY * (2 * ec + a))];
+    }
+    H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
+  }
+  const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
+  if constexpr (!ADJ) {
+    const int nq = lx + BX * (ly + BY * lz);
+    const R la = sLam[nq], m = sMu[nq];
+    const R tr = H[0][0] + H[1][1] + H[2][2];
+    Q[0] = -wq * (la * tr + 2 * m * H[0][0]);
+    Q[1] = -wq * (la * tr + 2 * m * H[1][1]);
+    Q[2] = -wq * (la * tr + 2 * m * H[2][2]);
+    Q[3] = -wq * (m * (H[1][2] + H[2][1]));
+    Q[4] = -wq * (m * (H[0][2] + H[2][0]));
+    Q[5] = -wq * (m * (H[0][1] + H[1][0]));
+  } else {
+    Q[0] = wq * H[0][0];
+    Q[1] = wq * H[1][1];
+    Q[2] = wq * H[2][2];
+    Q[3] = wq * (H[1][2] + H[2][1]);
+    Q[4] = wq * (H[0][2] + H[2][0]);
+    Q[5] = wq * (H[0][1] + H[1][0]);
+  }
+  return true;
+}
+
+// Phase 2: Q at every LGL point of the tile's bricks.
+template <typename R, int TX, int TY, int TZ, bool ADJ>
+__device__ __forceinline__ void pml_points(const Geo& g, int cx, int cy, int cz,
+                                           const R (&sW)[9][(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
+                                           const R (&sLam)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
+                                           const R (&sMu)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
+                                           R (&sQ)[6][27 * TX * TY * TZ]) {
+  constexpr int NP = 27 * TX * TY * TZ;
+  for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+    R Q[6];
+    if (!pml_point_value<R, TX, TY, TZ, ADJ>(g, cx, cy, cz, q, &sW[0][0], sLam, sMu, Q)) continue;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) sQ[v][q] = Q[v];
+  }
+}
+
+// Phase 3 for one box node (local lx, ly, lz): u-rows and S-rows, stored.
+template <typename R, int TX, int TY, int TZ>
+__device__ __forceinline__ void pml_node_rows(const Geo& g, const Tile& t, int cx, int cy, int cz, int lx, int ly,
+                                              int lz, const R (&sT)[9][(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
+                                              const R (&sQ)[6][27 * TX * TY * TZ], R* __restrict__ res,
+                                              const Part& PT) {
+  constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1;
+  const R s2h = R(2.0 / g.h);
+  const R vol = R(0.125 * g.h * g.h * g.h);
+  const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
+  const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
+  const size_t gp = (size_t)pml_index(g, gi, gj, gk);
+  int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
+  const int nex = node_bricks(lx, cx, exs, pxs);
+  const int ney = node_bricks(ly, cy, eys, pys);
+  const int nez = node_bricks(lz, cz, ezs, pzs);
+  // 1D weight sums of the tile's bricks that contain the node
+  const R Sx = R(wlgl(pxs[0]) + (nex > 1 ? wlgl(pxs[1]) : 0.0));
+  const R Sy = R(wlgl(pys[0]) + (ney > 1 ? wlgl(pys[1]) : 0.0));
+  const R Sz = R(wlgl(pzs[0]) + (nez > 1 ? wlgl(pzs[1]) : 0.0));
+  // u-rows: the stress-like tensor is nodal, so each direction factorizes
+  R dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0}, dz[3] = {0, 0, 0};
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    if (b >= nex) break;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R cf = R(dlgl(a, pxs[b]) * wlgl(a));
+      const int nx = (2 * exs[b] + a) + BX * (ly + BY * lz);
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) dx[ii] += cf * sT[3 * ii + 0][nx];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    if (b >= ney) break;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R cf = R(dlgl(a, pys[b]) * wlgl(a));
+      const int ny = lx + BX * ((2 * eys[b] + a) + BY * lz);
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) dy[ii] += cf * sT[3 * ii + 1][ny];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    if (b >= nez) break;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const R cf = R(dlgl(a, pzs[b]) * wlgl(a));
+      const int nz = lx + BX * (ly + BY * (2 * ezs[b] + a));
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) dz[ii] += cf * sT[3 * ii + 2][nz];
+    }
+  }
+  // S-rows: sum of the point values of every tile brick containing the node
+  R q6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int a3 = 0; a3 < 2; ++a3)
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+      for (int a1 = 0; a1 < 2; ++a1) {
+        if (a1 >= nex || a2 >= ney || a3 >= nez) continue;
+        const int qn = 27 * (exs[a1] + TX * (eys[a2] + TY * ezs[a3])) + pxs[a1] + 3 * pys[a2] + 9 * pzs[a3];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) q6[v] += sQ[v][qn];
+      }
+  const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+  const RowAddr ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
+  if (!is_dirichlet(g, gi, gj, gk)) {
+    const R f = vol * s2h;
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+      res[ra.u + ii * ra.us] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
+  }
+}
+
+// Per-node constants of phase 1: PML coefficients, history flag, indices.
+template <typename R>
+__device__ __forceinline__ void pml_node_setup(const Geo& g, int gi, int gj, int gk, R Le[3], R Lp[3], R Lw[3],
+                                               bool& hist, size_t& gnode, size_t& gp) {
+  gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
+  gp = (size_t)pml_index(g, gi, gj, gk);
+  const PmlCoef c = pml_coef_tab(g, gi, gj, gk);
+  hist = c.nbeta >= 2;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    Le[d] = R(c.Le[d]);
+    Lp[d] = R(c.Lp[d]);
+    Lw[d] = R(c.Lw[d]);
+  }
+}
+
+// One workgroup per (tile, source) (SRCLOOP = false) or per tile with the
+// sources in turn (SRCLOOP = true).
 template <typename R, int TX, int TY, int TZ, bool ADJ, bool SRCLOOP>
 __global__ void __launch_bounds__(PMLFWI_ETHREADS)
 pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
@@ -338,9 +561,9 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
   constexpr int NB = BX * BY * BZ, NP = 27 * TX * TY * TZ;
   __shared__ R sW[9][NB];   // [3k + i]: Le_kk u'_i + Lp_kk u_i + Lw_kk ubar_i
+  __shared__ R sQ[6][NP];
   __shared__ R sT[9][NB];   // [3i + k]: nodal stress-like tensor of the u-rows
   __shared__ R sLam[NB], sMu[NB];
-  __shared__ R sQ[6][NP];
 
   const int ti = xcd_tile();
   if (ti >= ntiles) return;
@@ -348,8 +571,6 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
   const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
   const size_t nn = (size_t)g.sn, np = (size_t)g.sp;
-  const R s2h = R(2.0 / g.h);
-  const R vol = R(0.125 * g.h * g.h * g.h);
 
   for (int n = threadIdx.x; n < NB; n += blockDim.x) {
     const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
@@ -363,179 +584,30 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   const int src0 = SRCLOOP ? 0 : (int)blockIdx.y, src1 = SRCLOOP ? nsrc : src0 + 1;
   for (int src = src0; src < src1; ++src) {
     const R* Y = Ybase + (size_t)src * ystride;
-    const R* P = Y + 6 * nn;
     for (int n = threadIdx.x; n < NB; n += blockDim.x) {
       const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
       if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
-      const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
-      const size_t gp = (size_t)pml_index(g, gi, gj, gk);
-      const PmlCoef c = pml_coef_tab(g, gi, gj, gk);
-      const bool hist = c.nbeta >= 2;
       R Le[3], Lp[3], Lw[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) { Le[d] = R(c.Le[d]); Lp[d] = R(c.Lp[d]); Lw[d] = R(c.Lw[d]); }
-      R u1[3], u2[3], u0[3], s0[6], s1[6], s2[6];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        u1[d] = Y[d * nn + gnode];
-        u2[d] = Y[(3 + d) * nn + gnode];
-        u0[d] = hist ? P[(P_X0U + d) * np + gp] : R(0);
-      }
-#pragma unroll
-      for (int v = 0; v < 6; ++v) {
-        s1[v] = P[(P_X1S + v) * np + gp];
-        s2[v] = P[(P_X2S + v) * np + gp];
-        s0[v] = hist ? P[(P_X0S + v) * np + gp] : R(0);
-      }
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) sW[3 * kk + ii][n] = Le[kk] * u2[ii] + Lp[kk] * u1[ii] + Lw[kk] * u0[ii];
-      if constexpr (!ADJ) {
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) {
-            const int v = vidx(ii, kk);
-            sT[3 * ii + kk][n] = Le[kk] * s2[v] + Lp[kk] * s1[v] + Lw[kk] * s0[v];
-          }
-      } else {
-        const R la = sLam[n], m = sMu[n];
-        const R t2 = s2[0] + s2[1] + s2[2], t1 = s1[0] + s1[1] + s1[2], t0 = s0[0] + s0[1] + s0[2];
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii)
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) {
-            const int v = vidx(ii, kk);
-            const R z = Le[kk] * s2[v] + Lp[kk] * s1[v] + Lw[kk] * s0[v];
-            R val = (ii == kk ? R(2) : R(1)) * m * z;
-            if (ii == kk) val += la * (Le[ii] * t2 + Lp[ii] * t1 + Lw[ii] * t0);
-            sT[3 * ii + kk][n] = -val;
-          }
-      }
+      bool hist;
+      size_t gnode, gp;
+      pml_node_setup<R>(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz, Le, Lp, Lw, hist, gnode, gp);
+      PmlNode<R> v;
+      pml_load_node<R>(Y, nn, np, gnode, gp, hist, v);
+      pml_node_fields<R, ADJ, NB>(v, Le, Lp, Lw, sLam[n], sMu[n], n, sW, sT);
     }
     __syncthreads();
-
-    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
-      const int pt = q % 27, e = q / 27;
-      const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
-      if (ea >= cx || eb >= cy || ec >= cz) continue;
-      const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
-      const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
-      R H[3][3];
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) {
-        R hx = 0, hy = 0, hz = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          hx += R(dlgl(qa, a)) * sW[0 + ii][(2 * ea + a) + BX * (ly + BY * lz)];
-          hy += R(dlgl(qb, a)) * sW[3 + ii][lx + BX * ((2 * eb + a) + BY * lz)];
-          hz += R(dlgl(qc, a)) * sW[6 + ii][lx + BX * (ly + BY * (2 * ec + a))];
-        }
-        H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
-      }
-      const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
-      if constexpr (!ADJ) {
-        const int nq = lx + BX * (ly + BY * lz);
-        const R la = sLam[nq], m = sMu[nq];
-        const R tr = H[0][0] + H[1][1] + H[2][2];
-        sQ[0][q] = -wq * (la * tr + 2 * m * H[0][0]);
-        sQ[1][q] = -wq * (la * tr + 2 * m * H[1][1]);
-        sQ[2][q] = -wq * (la * tr + 2 * m * H[2][2]);
-        sQ[3][q] = -wq * (m * (H[1][2] + H[2][1]));
-        sQ[4][q] = -wq * (m * (H[0][2] + H[2][0]));
-        sQ[5][q] = -wq * (m * (H[0][1] + H[1][0]));
-      } else {
-        sQ[0][q] = wq * H[0][0];
-        sQ[1][q] = wq * H[1][1];
-        sQ[2][q] = wq * H[2][2];
-        sQ[3][q] = wq * (H[1][2] + H[2][1]);
-        sQ[4][q] = wq * (H[0][2] + H[2][0]);
-        sQ[5][q] = wq * (H[0][1] + H[1][0]);
-      }
-    }
+    pml_points<R, TX, TY, TZ, ADJ>(g, cx, cy, cz, sW, sLam, sMu, sQ);
     __syncthreads();
-
+    R* res = rbase + (size_t)src * PT.per_src;
     for (int n = threadIdx.x; n < NB; n += blockDim.x) {
       const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
       if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
-      const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
-      const size_t gp = (size_t)pml_index(g, gi, gj, gk);
-      int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
-      const int nex = node_bricks(lx, cx, exs, pxs);
-      const int ney = node_bricks(ly, cy, eys, pys);
-      const int nez = node_bricks(lz, cz, ezs, pzs);
-      // 1D weight sums of the tile's bricks that contain the node
-      const R Sx = R(wlgl(pxs[0]) + (nex > 1 ? wlgl(pxs[1]) : 0.0));
-      const R Sy = R(wlgl(pys[0]) + (ney > 1 ? wlgl(pys[1]) : 0.0));
-      const R Sz = R(wlgl(pzs[0]) + (nez > 1 ? wlgl(pzs[1]) : 0.0));
-      // u-rows: the stress-like tensor is nodal, so each direction factorizes
-      R dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0}, dz[3] = {0, 0, 0};
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if (b >= nex) break;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const R cf = R(dlgl(a, pxs[b]) * wlgl(a));
-          const int nx = (2 * exs[b] + a) + BX * (ly + BY * lz);
-#pragma unroll
-          for (int ii = 0; ii < 3; ++ii) dx[ii] += cf * sT[3 * ii + 0][nx];
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if (b >= ney) break;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const R cf = R(dlgl(a, pys[b]) * wlgl(a));
-          const int ny = lx + BX * ((2 * eys[b] + a) + BY * lz);
-#pragma unroll
-          for (int ii = 0; ii < 3; ++ii) dy[ii] += cf * sT[3 * ii + 1][ny];
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if (b >= nez) break;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const R cf = R(dlgl(a, pzs[b]) * wlgl(a));
-          const int nz = lx + BX * (ly + BY * (2 * ezs[b] + a));
-#pragma unroll
-          for (int ii = 0; ii < 3; ++ii) dz[ii] += cf * sT[3 * ii + 2][nz];
-        }
-      }
-      // S-rows: sum of the point values of every tile brick containing the node
-      R q6[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-      for (int a3 = 0; a3 < 2; ++a3)
-#pragma unroll
-        for (int a2 = 0; a2 < 2; ++a2)
-#pragma unroll
-          for (int a1 = 0; a1 < 2; ++a1) {
-            if (a1 >= nex || a2 >= ney || a3 >= nez) continue;
-            const int qn = 27 * (exs[a1] + TX * (eys[a2] + TY * ezs[a3])) + pxs[a1] + 3 * pys[a2] + 9 * pzs[a3];
-#pragma unroll
-            for (int v = 0; v < 6; ++v) q6[v] += sQ[v][qn];
-          }
-      R* res = rbase + (size_t)src * PT.per_src;
-      const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
-      const RowAddr ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
-#pragma unroll
-      for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
-      if (!is_dirichlet(g, gi, gj, gk)) {
-        const R f = vol * s2h;
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii)
-          res[ra.u + ii * ra.us] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
-      }
+      pml_node_rows<R, TX, TY, TZ>(g, t, cx, cy, cz, lx, ly, lz, sT, sQ, res, PT);
     }
     __syncthreads();
   }
 }
 
-// ---------------------------------------------------------------------------
 // Nodal part of one RK4 stage.  With r the element residual of the stage input
 // Y, the rates are K = (x1|PML, x2, M^{-1}(f - r - nodal PML terms)) and
 //   mode 0:  acc = Xn + cA K,  Yout = Xn + cY K
