@@ -147,6 +147,18 @@ fwi_status fwi_adjoint_gradient(fwi_plan* plan, void* stream, const double* rho,
                                 const double* wavelet, const double* residual,
                                 void* workspace, double* g_lam, double* g_mu);
 
+/* The paper's own scheme for the adjoint and gradient (App. B, (B.2)-(B.4)
+ * with the transposes of (15), optimize-then-discretize): reverse-time RK4 of
+ * (15) from y(T) = 0 with the receiver residual as forcing at t_n, t_{n-1/2}
+ * (mean of the two step values) and t_{n-1}, and the gradient (C.1f)-(C.1g)
+ * integrated by the trapezoid rule over the step states.  Same arguments and
+ * call order as fwi_adjoint_gradient; the result differs from the exact
+ * discrete gradient by O(dt^2). */
+fwi_status fwi_adjoint_gradient_appb(fwi_plan* plan, void* stream, const double* rho,
+                                     const double* lam, const double* mu,
+                                     const double* wavelet, const double* residual,
+                                     void* workspace, double* g_lam, double* g_mu);
+
 /* Test hook: one application of the spatial operator to nodal fields.
  * x0, x1, x2, out: [nsrc][9][n_nodes] (3 displacement then 6 stress
  * components per node; entries off the unknowns are ignored / written 0).

@@ -61,6 +61,7 @@ _lib.fwi_plan_destroy.argtypes = [_P]
 _lib.fwi_forward.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_misfit.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.fwi_adjoint_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.fwi_adjoint_gradient_appb.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_apply_operator.argtypes = [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_timing_enable.argtypes = [_P, ctypes.c_int]
 _lib.fwi_timing_read.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -89,14 +90,14 @@ _lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _P]
 _lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]
 for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
-           "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
-           "fwi_adjoint_gradient", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
+           "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes", "fwi_status_string", "fwi_last_error")
@@ -185,6 +186,12 @@ def fwi_adjoint_gradient(plan, stream, rho, lam, mu, wavelet, residual, workspac
     _check(_lib.fwi_adjoint_gradient(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu),
                                      _ptr(wavelet), _ptr(residual), _ptr(workspace), _ptr(g_lam),
                                      _ptr(g_mu)), plan, "fwi_adjoint_gradient")
+
+
+def fwi_adjoint_gradient_appb(plan, stream, rho, lam, mu, wavelet, residual, workspace, g_lam, g_mu):
+    _check(_lib.fwi_adjoint_gradient_appb(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu),
+                                          _ptr(wavelet), _ptr(residual), _ptr(workspace), _ptr(g_lam),
+                                          _ptr(g_mu)), plan, "fwi_adjoint_gradient_appb")
 
 
 def fwi_apply_operator(plan, stream, which, rho, lam, mu, x0, x1, x2, workspace, out):

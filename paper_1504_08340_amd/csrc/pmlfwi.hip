@@ -310,6 +310,35 @@ __global__ void impulse_kernel(R* __restrict__ Y, long long reg, int sn, const R
   for (int d = 0; d < 3; ++d) atomic_add(&U[(size_t)(3 + d) * sn + node], R(scale * E[d]) * im);
 }
 
+// Receiver forcing of the paper's reverse RK4 (App. B) in one stage.  With
+// z = (y0, -y1, y2) the scheme is classical RK4 on the transposed operator
+// plus the rate -M^{-1} R^T r(t) in the x2 rows, r(t) = a_hi r_hi + a_lo r_lo
+// at the stage time; the stage combination the nodal kernel just applied gets
+// that rate's share: mode 0/1: Yout += cY g, acc += cA g; mode 2: Xn += cA g.
+template <typename R>
+__global__ void appb_force_kernel(R* __restrict__ Yout, R* __restrict__ Xn, R* __restrict__ acc, long long reg,
+                                  int sn, int mode, double cA, double cY, const R* __restrict__ invMu,
+                                  const int* __restrict__ rec, int nrec, const double* __restrict__ resid,
+                                  int n_hi, int n_lo, double a_hi, double a_lo, int nsteps) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (r >= nrec) return;
+  const size_t off = (size_t)src * reg;
+  const double* Eh = resid + ((size_t)src * (nsteps + 1) + n_hi) * nrec * 3 + (size_t)r * 3;
+  const double* El = resid + ((size_t)src * (nsteps + 1) + n_lo) * nrec * 3 + (size_t)r * 3;
+  const int node = rec[r];
+  const double im = (double)invMu[node];
+  for (int d = 0; d < 3; ++d) {
+    const double gval = -im * (a_hi * Eh[d] + a_lo * El[d]);
+    const size_t o = off + (size_t)(3 + d) * sn + node;
+    if (mode == 2) {
+      atomic_add(&Xn[o], R(cA * gval));
+    } else {
+      atomic_add(&Yout[o], R(cY * gval));
+      atomic_add(&acc[o], R(cA * gval));
+    }
+  }
+}
+
 __global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ obs,
                               double* __restrict__ resid, long long n, int per_step, int nsteps,
                               double half_dt, double* __restrict__ J) {
@@ -485,12 +514,13 @@ struct Run {
   // The interior and PML bricks write disjoint partial-array entries, so the
   // two launches may run at the same time: the interior one goes to the plan's
   // second stream when both lists are non-empty.
-  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw) {
+  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw, bool interior_only = false) {
     const Geo& G = g();
     const long long reg = (long long)L.reg_elems;
     const int ns = p->nsrc;
     hipStream_t si = st;
-    const bool fork = PMLFWI_CONCURRENT && !p->tiles_int.empty() && !p->tiles_pml.empty();
+    const bool pml = !interior_only && !p->tiles_pml.empty();
+    const bool fork = PMLFWI_CONCURRENT && !p->tiles_int.empty() && pml;
     if (fork) {
       if (!p->side) {
         HIP_TRY(p, hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
@@ -513,7 +543,7 @@ struct Run {
             G, p->d_tiles_int, nt, ns, Y, reg, lam(), mu(), res(), L.part, nullptr, 0, 0.0, nullptr, L.gpart);
     }
     if (fork) HIP_TRY(p, hipEventRecord(p->join_ev, si));
-    if (!p->tiles_pml.empty()) {
+    if (pml) {
       const int nt = (int)p->tiles_pml.size();
       const dim3 grid(8u * (unsigned)((nt + 7) / 8), SRCLOOP ? 1 : ns);
       TimedLaunch tl(p, adj ? FWI_K_PML_ADJ : FWI_K_PML, st);
@@ -659,6 +689,62 @@ struct Run {
       for (int n = b - 1; n >= a; --n) {
         if ((e = step(true, ra, n, nullptr, -1, false, n - a)) != FWI_OK) return e;
         if (n > 0 && (e = impulse(ra, resid, n)) != FWI_OK) return e;
+      }
+    }
+    gradient_reduce_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
+    HIP_TRY(p, hipGetLastError());
+    return FWI_OK;
+  }
+
+  // The paper's reverse-time RK4 of the adjoint problem (App. B): from
+  // y(T) = 0, step n (t_{n+1} -> t_n) is classical RK4 on the transposed
+  // operator for z = (y0, -y1, y2) with the receiver residual as forcing at
+  // the stage times (r_{n+1}, the mean of r_{n+1} and r_n twice, r_n); the
+  // gradient (C.1f)-(C.1g) is the trapezoid rule over the step states:
+  // g += dt w_n z1^T (dK_RD/dm) u^n.
+  fwi_status adjoint_appb(const double* rho, const double* lam_, const double* mu_, const double* wav,
+                          const double* resid, double* gl, double* gm) {
+    static const double cA[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+    static const double cY[4] = {0.5, 0.5, 1.0, 0.0};
+    const fwi_problem& P = p->prob;
+    const Geo& G = g();
+    const double dt = P.dt;
+    fwi_status e;
+    if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
+    if ((e = fill<double>(gacc(), (size_t)L.gpart.per_src, 0.0)) != FWI_OK) return e;
+    const bool keep_all = P.ckpt_every == 0;
+    const int ra = keep_all ? 0 : 4;
+    if ((e = zero_regs(ra, 4)) != FWI_OK) return e;
+    const int k = keep_all ? P.nsteps : P.ckpt_every;
+    const int nseg = (P.nsteps + k - 1) / k;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int a = sg * k, b = std::min(P.nsteps, a + k);
+      if (!keep_all) {
+        HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(sg), (size_t)P.nsrc * L.reg_elems * L.es,
+                                  hipMemcpyDeviceToDevice, st));
+        if ((e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
+        for (int n = a; n < b; ++n)
+          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
+      }
+      for (int n = b - 1; n >= a; --n) {
+        R* Xn = reg(ra);
+        R* outs[4] = {reg(ra + 1), reg(ra + 2), reg(ra + 1), nullptr};
+        R* in = Xn;
+        for (int s = 0; s < 4; ++s) {
+          if ((e = elements(true, in, nullptr, 0.0)) != FWI_OK) return e;
+          if ((e = nodal(s, in, outs[s], Xn, reg(ra + 3), nullptr, n, nullptr)) != FWI_OK) return e;
+          if (p->nrec > 0) {
+            const int mode = s == 0 ? 0 : (s == 3 ? 2 : 1);
+            const double ah = s == 0 ? 1.0 : (s == 3 ? 0.0 : 0.5), al = 1.0 - ah;
+            appb_force_kernel<R><<<dim3(blocks(p->nrec, 128), P.nsrc), 128, 0, st>>>(
+                outs[s], Xn, reg(ra + 3), (long long)L.reg_elems, G.sn, mode, cA[s] * dt, cY[s] * dt, invm(),
+                p->d_rec, p->nrec, resid, n + 1, n, ah, al, P.nsteps);
+            HIP_TRY(p, hipGetLastError());
+          }
+          in = outs[s];
+        }
+        const double w = (n == 0 || n == P.nsteps) ? 0.5 : 1.0;
+        if ((e = elements(true, Xn, store(n - a, 0), dt * w, true)) != FWI_OK) return e;
       }
     }
     gradient_reduce_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
@@ -862,6 +948,18 @@ fwi_status fwi_adjoint_gradient(fwi_plan* p, void* stream, const double* rho, co
     return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient: no fwi_forward on this workspace");
   return dispatch(p, (hipStream_t)stream, workspace,
                   [&](auto& r) { return r.adjoint(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
+}
+
+fwi_status fwi_adjoint_gradient_appb(fwi_plan* p, void* stream, const double* rho, const double* lam,
+                                     const double* mu, const double* wavelet, const double* residual,
+                                     void* workspace, double* g_lam, double* g_mu) {
+  if (!p) return FWI_ERR_ARG;
+  if (!rho || !lam || !mu || !wavelet || !workspace || !g_lam || !g_mu || (p->nrec > 0 && !residual))
+    return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient_appb: null pointer");
+  if (p->fwd_ws != workspace)
+    return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient_appb: no fwi_forward on this workspace");
+  return dispatch(p, (hipStream_t)stream, workspace,
+                  [&](auto& r) { return r.adjoint_appb(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
 }
 
 fwi_status fwi_apply_operator(fwi_plan* p, void* stream, int which, const double* rho, const double* lam,

@@ -69,12 +69,15 @@ class Solver:
         B.fwi_misfit(self.plan, stream, traces, observed, residual, J)
         return J, residual
 
-    def adjoint_gradient(self, rho, lam, mu, wavelet, residual, g_lam=None, g_mu=None, stream=None):
+    def adjoint_gradient(self, rho, lam, mu, wavelet, residual, g_lam=None, g_mu=None, stream=None,
+                         scheme="discrete"):
+        """scheme "discrete": exact derivative of the discrete misfit; "appb": the
+        paper's reverse-time RK4 of App. B (optimize-then-discretize)."""
         n = int(self.sizes.n_int_nodes)
         g_lam = torch.empty(n, dtype=torch.float64, device=self.device) if g_lam is None else g_lam
         g_mu = torch.empty(n, dtype=torch.float64, device=self.device) if g_mu is None else g_mu
-        B.fwi_adjoint_gradient(self.plan, stream, rho, lam, mu, wavelet, residual, self.workspace,
-                               g_lam, g_mu)
+        fn = {"discrete": B.fwi_adjoint_gradient, "appb": B.fwi_adjoint_gradient_appb}[scheme]
+        fn(self.plan, stream, rho, lam, mu, wavelet, residual, self.workspace, g_lam, g_mu)
         return g_lam, g_mu
 
     def apply_operator(self, which, rho, lam, mu, x0, x1, x2, out=None, stream=None):

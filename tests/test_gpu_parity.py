@@ -109,3 +109,25 @@ def test_bad_receiver_node_is_rejected(P):
     wl = workload("tiny")
     with pytest.raises(P.FwiError):
         P.Solver(wl.prob, wl.src_node, wl.src_dir, np.array([0], np.int32))   # Dirichlet corner
+
+
+@pytest.mark.parametrize("name,ckpt,prec", [("tiny", 0, 0), ("tiny", 7, 0), ("tiny_ragged", 0, 0),
+                                            ("tiny_3src", 4, 0), ("cfg1_100", 0, 0), ("cfg1_100", 0, 1)])
+def test_appendix_b_gradient_vs_oracle(P, name, ckpt, prec):
+    """The paper's reverse-time RK4 (App. B) against the oracle's App. B."""
+    import torch
+    wl = workload(name)
+    _, st = oracle_system(name)
+    tr_o, states = st.forward(wl.wavelet, store=True)
+    obs = observed(name)
+    gl_o, gm_o = st.adjoint_gradient_appb(wl.wavelet, obs, states)
+    S = _solver(P, wl, prec, ckpt)
+    rho, lam, mu, wav = _inputs(S, wl)
+    tr = S.forward(rho, lam, mu, wav)
+    J, res = S.misfit(tr, S.tensor(obs))
+    gl, gm = S.adjoint_gradient(rho, lam, mu, wav, res, scheme="appb")
+    torch.cuda.synchronize()
+    tol = 1e-9 if prec == 0 else 1e-4
+    e = (rel_l2(gl.cpu().numpy(), gl_o), rel_l2(gm.cpu().numpy(), gm_o))
+    print(f"{name} ckpt {ckpt} precision {prec}: App. B g_lam {e[0]:.2e} g_mu {e[1]:.2e}")
+    assert e[0] <= tol and e[1] <= tol
