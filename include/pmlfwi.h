@@ -190,6 +190,19 @@ fwi_status fwi_material_mass(fwi_plan* plan, void* stream, double* mdiag);
 fwi_status fwi_gradient_finalize(fwi_plan* plan, void* stream, const double* g_mis,
                                  const double* g_reg, double R, double* g);
 
+/* Model check (synchronizes the stream; rho, lam, mu on the device, info a
+ * host array of 6 doubles): info = [min rho, min mu, min (3 lam + 2 mu),
+ * max vp, omega_max bound, largest stable dt].  The bound on the largest
+ * frequency of the interior operator is element by element: for every
+ * interior brick, (max(lam, 0) c_lam + max mu c_mu) (2/h)^2 / min rho with
+ * c_lam, c_mu the largest eigenvalues of the unit LGL reference brick; the
+ * PML stretching only lowers stiffness per mass.  RK4 is stable for
+ * dt omega_max <= 2 sqrt(2).  Returns FWI_ERR_ARG when rho, mu or the bulk
+ * term 3 lam + 2 mu is not positive, FWI_ERR_UNSTABLE when the plan's dt
+ * exceeds info[5]. */
+fwi_status fwi_check_model(fwi_plan* plan, void* stream, const double* rho,
+                           const double* lam, const double* mu, double* info);
+
 /* out[0] = sum_i a_i b_i w_i (w null: weights 1), device vectors of length n;
  * one workgroup, fixed summation order (deterministic).  Used for the norms
  * of (24) and the inner products of the line search (Algorithm 1). */

@@ -11,7 +11,8 @@ C ABI declared in ``include/pmlfwi.h``.
 """
 from .binding import (FWI_FP32, FWI_FP32_BF16X3, FWI_FP32_MFMA, FWI_FP64,  # noqa: F401
                       FWI_REG_TIKHONOV, FWI_REG_TV,
-                      FwiError, fwi_adjoint_gradient, fwi_adjoint_gradient_appb, fwi_apply_operator, fwi_dot,
+                      FwiError, fwi_adjoint_gradient, fwi_adjoint_gradient_appb, fwi_apply_operator,
+                      fwi_check_model, fwi_dot,
                       fwi_forward, fwi_gradient_finalize, fwi_last_error, fwi_material_mass,
                       fwi_misfit, fwi_plan_create, fwi_plan_destroy, fwi_query,
                       fwi_regularization, fwi_status_string, fwi_timing_enable,

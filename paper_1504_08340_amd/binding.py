@@ -74,6 +74,7 @@ _lib.fwi_regularization.argtypes = [_P, _P, ctypes.c_int, ctypes.c_double, _P, _
 _lib.fwi_material_mass.argtypes = [_P, _P, _P]
 _lib.fwi_gradient_finalize.argtypes = [_P, _P, _P, _P, ctypes.c_double, _P]
 _lib.fwi_dot.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
+_lib.fwi_check_model.argtypes = [_P, _P, _P, _P, _P, _P]
 
 
 class fwi_conv_shape(ctypes.Structure):
@@ -91,14 +92,14 @@ _lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c
 _lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]
 for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
-           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
-           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot",
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes", "fwi_status_string", "fwi_last_error")
 FWI_REG_TIKHONOV, FWI_REG_TV = 0, 1
@@ -212,6 +213,15 @@ def fwi_material_mass(plan, stream, mdiag):
 def fwi_gradient_finalize(plan, stream, g_mis, g_reg, R, g):
     _check(_lib.fwi_gradient_finalize(plan, _stream(stream), _ptr(g_mis), _ptr(g_reg), float(R), _ptr(g)),
            plan, "fwi_gradient_finalize")
+
+
+def fwi_check_model(plan, stream, rho, lam, mu):
+    """Returns the 6 host values of fwi_check_model; raises FwiError on a
+    non-physical model (FWI_ERR_ARG) or an unstable dt (FWI_ERR_UNSTABLE)."""
+    info = (ctypes.c_double * 6)()
+    _check(_lib.fwi_check_model(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu), info), plan,
+           "fwi_check_model")
+    return list(info)
 
 
 def fwi_dot(stream, n, a, b, w, out):

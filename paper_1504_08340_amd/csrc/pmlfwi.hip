@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "pmlfwi.h"
+#include <cmath>
 #include <type_traits>
 
 #include "kernels.h"
@@ -48,6 +49,10 @@ struct fwi_plan {
   // (fork and join through events on the caller's stream)
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // largest eigenvalues of M^{-1} K for the unit reference brick with lam = 1,
+  // mu = 0 and lam = 0, mu = 1 (stability bound of fwi_check_model)
+  double c_lam = 0.0, c_mu = 0.0;
+  double* d_info = nullptr;   // 5 doubles: device result of the model check
 };
 
 namespace {
@@ -144,6 +149,65 @@ std::vector<Seg> axis_segments(int lo_pml, int n_int, int hi_pml, int T) {
   for (int e = lo_pml + n_int; e < lo_pml + n_int + hi_pml; e += T)
     s.push_back({e, std::min(T, lo_pml + n_int + hi_pml - e), false});
   return s;
+}
+
+// Largest eigenvalue of M^{-1} K for the reference brick [-1,1]^3 with the
+// 3x3x3 LGL rule, K = sum_q w_q (lam (div)^T div + mu 2 eps^T : eps), M the
+// lumped mass diag(w_a) per component; symmetric power iteration on
+// M^{-1/2} K M^{-1/2} (host, 81 x 81).
+double reference_eigen(double lam, double mu) {
+  const double w1[3] = {1.0 / 3, 4.0 / 3, 1.0 / 3};
+  const double D[3][3] = {{-1.5, 2.0, -0.5}, {-0.5, 0.0, 0.5}, {0.5, -2.0, 1.5}};   // D[q][a]
+  std::vector<double> K(81 * 81, 0.0);
+  for (int q = 0; q < 27; ++q) {
+    const int qi[3] = {q % 3, (q / 3) % 3, q / 9};
+    const double wq = w1[qi[0]] * w1[qi[1]] * w1[qi[2]];
+    // G[k][i][col]: d_k u_i at q per unknown col = 3 a + i
+    std::vector<double> G(9 * 81, 0.0);
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 3; ++a) {
+        int ai[3] = {qi[0], qi[1], qi[2]};
+        ai[k] = a;
+        const int node = ai[0] + 3 * ai[1] + 9 * ai[2];
+        for (int i = 0; i < 3; ++i) G[(3 * k + i) * 81 + 3 * node + i] += D[qi[k]][a];
+      }
+    for (int r = 0; r < 81; ++r)
+      for (int c = 0; c < 81; ++c) {
+        const double divr = G[0 * 81 + r] + G[4 * 81 + r] + G[8 * 81 + r];
+        const double divc = G[0 * 81 + c] + G[4 * 81 + c] + G[8 * 81 + c];
+        double ee = 0.0;
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) {
+            const double er = 0.5 * (G[(3 * k + i) * 81 + r] + G[(3 * i + k) * 81 + r]);
+            const double ec = 0.5 * (G[(3 * k + i) * 81 + c] + G[(3 * i + k) * 81 + c]);
+            ee += er * ec;
+          }
+        K[r * 81 + c] += wq * (lam * divr * divc + mu * 2.0 * ee);
+      }
+  }
+  std::vector<double> isq(81);
+  for (int a = 0; a < 27; ++a)
+    for (int i = 0; i < 3; ++i) isq[3 * a + i] = 1.0 / std::sqrt(w1[a % 3] * w1[(a / 3) % 3] * w1[a / 9]);
+  std::vector<double> x(81), y(81);
+  for (int r = 0; r < 81; ++r) x[r] = 1.0 + 0.01 * r;
+  double ev = 0.0;
+  for (int it = 0; it < 3000; ++it) {
+    double nrm = 0.0;
+    for (int r = 0; r < 81; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < 81; ++c) acc += K[r * 81 + c] * isq[c] * x[c];
+      y[r] = isq[r] * acc;
+      nrm += y[r] * y[r];
+    }
+    nrm = std::sqrt(nrm);
+    double dot = 0.0;
+    for (int r = 0; r < 81; ++r) dot += x[r] * y[r];
+    double xx = 0.0;
+    for (int r = 0; r < 81; ++r) xx += x[r] * x[r];
+    ev = dot / xx;
+    for (int r = 0; r < 81; ++r) x[r] = y[r] / nrm;
+  }
+  return ev;
 }
 
 void build_tiles(fwi_plan* p) {
@@ -388,6 +452,50 @@ __global__ void gradient_reduce_kernel(Geo g, const double* __restrict__ gacc, P
   }
   g_lam[mi] = a;
   g_mu[mi] = b;
+}
+
+// out = [min rho, min mu, min (3 lam + 2 mu), max vp, max over interior bricks of
+// (max(lam, 0) c_lam + max mu c_mu) / min rho] (nodal values of each brick):
+// one workgroup, fixed order.
+__global__ void __launch_bounds__(1024) model_check_kernel(Geo g, const double* __restrict__ rho,
+                                                           const double* __restrict__ lam,
+                                                           const double* __restrict__ mu, double c_lam,
+                                                           double c_mu, double* __restrict__ out) {
+  __shared__ double red[5][1024];
+  double mr = 1e300, mm = 1e300, mk = 1e300, vp = 0.0, wb = 0.0;
+  for (int j = threadIdx.x; j < g.n_int; j += blockDim.x) {
+    mr = fmin(mr, rho[j]);
+    mm = fmin(mm, mu[j]);
+    mk = fmin(mk, 3.0 * lam[j] + 2.0 * mu[j]);
+    if (rho[j] > 0.0 && lam[j] + 2.0 * mu[j] > 0.0) vp = fmax(vp, sqrt((lam[j] + 2.0 * mu[j]) / rho[j]));
+  }
+  const long long nb = (long long)g.ex * g.ey * g.ez;
+  for (long long e = threadIdx.x; e < nb; e += blockDim.x) {
+    const int ex = (int)(e % g.ex), ey = (int)((e / g.ex) % g.ey), ez = (int)(e / ((long long)g.ex * g.ey));
+    double lmax = 0.0, mmax = 0.0, rmin = 1e300;
+    for (int c = 0; c < 27; ++c) {
+      const int j = (2 * ex + c % 3) + g.NIX * ((2 * ey + (c / 3) % 3) + g.NIY * (2 * ez + c / 9));
+      lmax = fmax(lmax, lam[j]);
+      mmax = fmax(mmax, mu[j]);
+      rmin = fmin(rmin, rho[j]);
+    }
+    if (rmin > 0.0) wb = fmax(wb, (lmax * c_lam + mmax * c_mu) / rmin);
+  }
+  red[0][threadIdx.x] = mr;
+  red[1][threadIdx.x] = mm;
+  red[2][threadIdx.x] = mk;
+  red[3][threadIdx.x] = vp;
+  red[4][threadIdx.x] = wb;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+      for (int k = 3; k < 5; ++k) red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) out[k] = red[k][0];
 }
 
 // Nodal test fields [nsrc][9][n_nodes] <-> register slot (0: x0, 1: x1, 2: x2).
@@ -830,6 +938,8 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   for (int r = 0; r < prob->nrec; ++r)
     if (bad_node(rec_node[r])) { delete p; return FWI_ERR_ARG; }
   build_tiles(p);
+  p->c_lam = reference_eigen(1.0, 0.0);
+  p->c_mu = reference_eigen(0.0, 1.0);
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
     hipError_t e = hipMalloc(dst, bytes);
@@ -851,6 +961,8 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   step("receiver nodes", (void**)&p->d_rec, rec_node, prob->nrec * sizeof(int32_t));
   step("axis tables", (void**)&p->d_tab, p->tab.data(), p->tab.size() * sizeof(double));
   step("face ordinals", (void**)&p->d_fo, p->fo.data(), p->fo.size() * sizeof(int));
+  const double zeros[5] = {0, 0, 0, 0, 0};
+  step("model-check buffer", (void**)&p->d_info, zeros, sizeof(zeros));
   p->g.tab = p->d_tab;
   p->g.fo = p->d_fo;
   if (e != hipSuccess) {
@@ -906,6 +1018,7 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
   (void)hipFree(p->d_rec);
   (void)hipFree(p->d_tab);
   (void)hipFree(p->d_fo);
+  (void)hipFree(p->d_info);
   delete p;
   return FWI_OK;
 }
@@ -1004,6 +1117,32 @@ fwi_status fwi_gradient_finalize(fwi_plan* p, void* stream, const double* g_mis,
   if (!g_mis || !g || (R != 0.0 && !g_reg)) return fail(p, FWI_ERR_ARG, "fwi_gradient_finalize: null pointer");
   gradient_finalize_kernel<<<blocks(p->g.n_int, 256), 256, 0, (hipStream_t)stream>>>(p->g, g_mis, g_reg, R, g);
   HIP_TRY(p, hipGetLastError());
+  return FWI_OK;
+}
+
+fwi_status fwi_check_model(fwi_plan* p, void* stream, const double* rho, const double* lam, const double* mu,
+                           double* info) {
+  if (!p) return FWI_ERR_ARG;
+  if (!rho || !lam || !mu || !info) return fail(p, FWI_ERR_ARG, "fwi_check_model: null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  double* d = nullptr;
+  d = p->d_info;
+  model_check_kernel<<<1, 1024, 0, st>>>(p->g, rho, lam, mu, p->c_lam, p->c_mu, d);
+  hipError_t e = hipGetLastError();
+  double v[5] = {0, 0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(v, d, sizeof(v), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  HIP_TRY(p, e);
+  // omega_max^2 <= max over bricks of the brick bound; the unit reference brick
+  // has edge 2, so a brick of edge h scales it by (2/h)^2
+  const double h = p->g.h;
+  const double wmax = std::sqrt(v[4] * 4.0 / (h * h));
+  for (int k = 0; k < 4; ++k) info[k] = v[k];
+  info[4] = wmax;
+  info[5] = wmax > 0 ? 2.0 * std::sqrt(2.0) / wmax : HUGE_VAL;
+  if (!(v[0] > 0.0) || !(v[1] > 0.0) || !(v[2] > 0.0))
+    return fail(p, FWI_ERR_ARG, "fwi_check_model: rho, mu and 3 lam + 2 mu must be positive");
+  if (p->prob.dt > info[5]) return fail(p, FWI_ERR_UNSTABLE, "fwi_check_model: dt above the RK4 stability bound");
   return FWI_OK;
 }
 

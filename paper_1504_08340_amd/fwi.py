@@ -78,7 +78,16 @@ class FwiStage:
         self.counts = [0, 0]
 
     def forward(self, lam, mu):
+        """J_mis of the model; +inf for a model the solver must not run (non-positive
+        rho, mu or bulk term, or a time step above the model's stability bound),
+        which the line search then rejects."""
         lam, mu = lam.contiguous(), mu.contiguous()
+        try:
+            B.fwi_check_model(self.S.plan, None, self.rho, lam, mu)
+        except B.FwiError:
+            self.last_J = float("inf")
+            self._lam = None
+            return self.last_J
         tr = self.S.forward(self.rho, lam, mu, self.wav)
         _, self._res = self.S.misfit(tr, self.obs, J=self._J)
         self._lam, self._mu = lam, mu

@@ -1,0 +1,72 @@
+"""Model validation and the RK4 stability bound (fwi_check_model).
+
+The bound on the largest frequency must lie above the true largest
+frequency of the interior operator (the oracle's eigenvalue of M^{-1} K for a
+homogeneous box) and not far above it; a time step past the bound and
+non-physical materials must be rejected with their status codes; the
+workloads this library runs pass the check.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1504_08340_amd as pkg
+    return pkg
+
+
+def test_bound_is_above_and_close_to_the_true_frequency(P):
+    import scipy.sparse.linalg as spla
+    from oracle.assemble import free_box_stiffness
+    wl = W.tiny(ne_int=(3, 3, 2), npml_side=1, npml_bottom=1, nsteps=5, seed=3)
+    lam0, mu0, rho0 = 4.0e7, 2.0e7, 2000.0
+    S = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    n = wl.lam.size
+    info = P.fwi_check_model(S.plan, None, S.tensor(np.full(n, rho0)), S.tensor(np.full(n, lam0)),
+                             S.tensor(np.full(n, mu0)))
+    assert info[0] == rho0 and info[1] == mu0 and info[2] == 3 * lam0 + 2 * mu0
+    assert info[3] == pytest.approx(np.sqrt((lam0 + 2 * mu0) / rho0))
+    K, Md, _ = free_box_stiffness((4, 4, 4), wl.prob.h, lambda p: np.full(p.shape[0], lam0),
+                                  lambda p: np.full(p.shape[0], mu0), rho=rho0)
+    Ms = 1.0 / np.sqrt(Md)
+    A = (K.multiply(Ms[:, None])).multiply(Ms[None, :]).tocsr()
+    w_true = np.sqrt(spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0])
+    print(f"omega bound {info[4]:.2f}, true {w_true:.2f}, ratio {info[4] / w_true:.3f}")
+    assert w_true <= info[4] <= 1.5 * w_true
+    assert info[5] == pytest.approx(2 * np.sqrt(2) / info[4])
+    S.close()
+
+
+def test_unstable_step_and_bad_materials_are_rejected(P):
+    wl = W.tiny(ne_int=(2, 2, 2), npml_side=1, npml_bottom=1, nsteps=5, seed=3)
+    S = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    rho, lam, mu = (S.tensor(a) for a in (wl.rho, wl.lam, wl.mu))
+    info = P.fwi_check_model(S.plan, None, rho, lam, mu)
+    S.close()
+    fast = wl.prob.replace(dt=2.0 * info[5])
+    S2 = P.Solver(fast, wl.src_node, wl.src_dir, wl.rec_node)
+    with pytest.raises(P.FwiError, match="stability"):
+        P.fwi_check_model(S2.plan, None, S2.tensor(wl.rho), S2.tensor(wl.lam), S2.tensor(wl.mu))
+    bad = wl.mu.copy()
+    bad[7] = -1.0
+    with pytest.raises(P.FwiError, match="positive"):
+        P.fwi_check_model(S2.plan, None, S2.tensor(wl.rho), S2.tensor(wl.lam), S2.tensor(bad))
+    S2.close()
+
+
+@pytest.mark.parametrize("make", [W.config1, W.config2, W.config3])
+def test_workloads_pass_the_check(P, make):
+    wl = make(nsteps=5)
+    S = P.Solver(wl.prob, wl.src_node[:1], wl.src_dir[:1], wl.rec_node)
+    info = P.fwi_check_model(S.plan, None, S.tensor(wl.rho), S.tensor(wl.lam), S.tensor(wl.mu))
+    print(f"{wl.name}: dt {wl.prob.dt:.3e} <= stable {info[5]:.3e}")
+    assert wl.prob.dt <= info[5]
+    S.close()
