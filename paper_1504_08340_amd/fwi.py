@@ -156,6 +156,9 @@ def invert(stages, lam0, mu0, mass, opts: FwiOptions, history: FwiHistory | None
             break
         pairs = []
         Jm = st.forward(lam, mu)
+        if Jm == float("inf"):
+            raise ValueError("the start model fails fwi_check_model (non-physical materials or "
+                             "a time step above its stability bound)")
         gl_mis, gm_mis = st.gradient()
         for k in range(opts.max_iter):
             if Jm <= opts.tol:
