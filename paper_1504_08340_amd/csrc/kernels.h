@@ -136,6 +136,18 @@ __device__ __forceinline__ int node_bricks(int l, int cnt, int* e, int* p) {
   return n;
 }
 
+// The two candidate bricks of a tile along one axis for local node l
+// (0 <= l <= 2 cnt): the brick below (l odd: the only one) and the brick above
+// (l even), as offsets se * brick + sp * (position of the node in the brick)
+// into brick-local arrays, each with a flag telling whether it holds the node.
+__device__ __forceinline__ void axis_bricks(int l, int cnt, int se, int sp, int o[2], bool v[2]) {
+  const int e0 = (l - 1) >> 1, e1 = l >> 1;
+  o[0] = se * e0 + sp * (l - 2 * e0);
+  o[1] = se * e1 + sp * (l - 2 * e1);
+  v[0] = l >= 1;
+  v[1] = !(l & 1) && e1 < cnt;
+}
+
 template <typename R>
 __device__ __forceinline__ void atomic_add(R* p, R v) {
   unsafeAtomicAdd(p, v);
@@ -159,6 +171,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
   __shared__ R sU[3][NB];
   __shared__ R sLam[NB], sMu[NB];
   __shared__ R sS[6][NP];
+  __shared__ R sR[3][NP];   // brick-local rows B^T S, summed over bricks per node below
   __shared__ R sV[GRAD ? 3 : 1][GRAD ? NB : 1];
   __shared__ R sG[GRAD ? 2 : 1][GRAD ? NP : 1];
   __shared__ double sGacc[GRAD ? 2 : 1][GRAD ? NB : 1];   // summed over sources
@@ -254,15 +267,39 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
     }
     __syncthreads();
 
+    // brick-local rows: for local node (pa, pb, pc) of brick e and component i,
+    // sum over the points on the three lines through the node of
+    // D(point, node) times the stress column of that axis (sum-factorized B^T S)
+    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+      const int pt = q % 27, e0 = q - pt;
+      const int pa = pt % 3, pb = (pt / 3) % 3, pc = pt / 9;
+      R r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const R cxa = R(dlgl(a, pa)), cya = R(dlgl(a, pb)), cza = R(dlgl(a, pc));
+        const int qx = e0 + a + 3 * pb + 9 * pc;
+        const int qy = e0 + pa + 3 * a + 9 * pc;
+        const int qz = e0 + pa + 3 * pb + 9 * a;
+        r0 += cxa * sS[0][qx] + cya * sS[5][qy] + cza * sS[4][qz];
+        r1 += cxa * sS[5][qx] + cya * sS[1][qy] + cza * sS[3][qz];
+        r2 += cxa * sS[4][qx] + cya * sS[3][qy] + cza * sS[2][qz];
+      }
+      sR[0][q] = r0;
+      sR[1][q] = r1;
+      sR[2][q] = r2;
+    }
+    __syncthreads();
+
     R* res = rbase + (size_t)src * PT.per_src;
     for (int n = threadIdx.x; n < NB; n += blockDim.x) {
       const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
       if (lx >= nbx || ly >= nby || lz >= nbz) continue;
       const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-      int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
-      const int nex = node_bricks(lx, cx, exs, pxs);
-      const int ney = node_bricks(ly, cy, eys, pys);
-      const int nez = node_bricks(lz, cz, ezs, pzs);
+      int ox[2], oy[2], oz[2];
+      bool vx[2], vy[2], vz[2];
+      axis_bricks(lx, cx, 27, 1, ox, vx);
+      axis_bricks(ly, cy, 27 * TX, 3, oy, vy);
+      axis_bricks(lz, cz, 27 * TX * TY, 9, oz, vz);
       R r0 = 0, r1 = 0, r2 = 0;
       R gl = 0, gm = 0;
 #pragma unroll
@@ -271,22 +308,12 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
         for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
           for (int a1 = 0; a1 < 2; ++a1) {
-            if (a1 >= nex || a2 >= ney || a3 >= nez) continue;
-            const int ea = exs[a1], eb = eys[a2], ec = ezs[a3];
-            const int pa = pxs[a1], pb = pys[a2], pc = pzs[a3];
-            const int eb0 = 27 * (ea + TX * (eb + TY * ec));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const R cxa = R(dlgl(a, pa)), cya = R(dlgl(a, pb)), cza = R(dlgl(a, pc));
-              const int qx = eb0 + a + 3 * pb + 9 * pc;
-              const int qy = eb0 + pa + 3 * a + 9 * pc;
-              const int qz = eb0 + pa + 3 * pb + 9 * a;
-              r0 += cxa * sS[0][qx] + cya * sS[5][qy] + cza * sS[4][qz];
-              r1 += cxa * sS[5][qx] + cya * sS[1][qy] + cza * sS[3][qz];
-              r2 += cxa * sS[4][qx] + cya * sS[3][qy] + cza * sS[2][qz];
-            }
+            if (!(vx[a1] && vy[a2] && vz[a3])) continue;
+            const int qn = ox[a1] + oy[a2] + oz[a3];
+            r0 += sR[0][qn];
+            r1 += sR[1][qn];
+            r2 += sR[2][qn];
             if constexpr (GRAD) {
-              const int qn = eb0 + pa + 3 * pb + 9 * pc;
               gl += sG[0][qn];
               gm += sG[1][qn];
             }
@@ -331,42 +358,57 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
 //            Z_k = Le_kk T2 + Lp_kk T1 + Lw_kk T0 (symmetric stress-like fields)
 //   S-rows:  r_S += int T~_ab (H_ab + H_ba)  (a != b),  H_aa  (a = b).
 //
-// A workgroup works in three phases per source: (1) every box node's register
-// values become the nodal fields W and T in LDS, (2) every LGL point of every
-// brick forms Q from the gradients of W, (3) every box node sums its u-rows
-// (factorized over the axes, T being nodal) and S-rows and stores them.
+// The S-rows depend on the displacements only (through W and Q) and the
+// u-rows on the stresses only (through T), so the operator splits into two
+// independent parts (PART: PML_SROWS, PML_UROWS or both).  A workgroup works
+// in up to three phases per source: (1) every box node's register values
+// become the nodal fields W and/or T in LDS, (2) S-rows: every LGL point of
+// every brick forms Q from the gradients of W, (3) every box node sums its
+// u-rows (a stencil along each axis, T being nodal) and/or S-rows and stores
+// them.
+enum { PML_SROWS = 1, PML_UROWS = 2, PML_ALL = 3 };
 
 template <typename R>
 struct PmlNode {          // register values of one box node for one source
   R u1[3], u2[3], u0[3], s0[6], s1[6], s2[6];
 };
 
-template <typename R>
+template <typename R, bool U, bool S>
 __device__ __forceinline__ void pml_load_node(const R* __restrict__ Y, size_t nn, size_t np, size_t gnode,
                                               size_t gp, bool hist, PmlNode<R>& v) {
   const R* P = Y + 6 * nn;
+  if constexpr (U) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    v.u1[d] = Y[d * nn + gnode];
-    v.u2[d] = Y[(3 + d) * nn + gnode];
-    v.u0[d] = hist ? P[(P_X0U + d) * np + gp] : R(0);
+    for (int d = 0; d < 3; ++d) {
+      v.u1[d] = Y[d * nn + gnode];
+      v.u2[d] = Y[(3 + d) * nn + gnode];
+      v.u0[d] = hist ? P[(P_X0U + d) * np + gp] : R(0);
+    }
   }
+  if constexpr (S) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    v.s1[c] = P[(P_X1S + c) * np + gp];
-    v.s2[c] = P[(P_X2S + c) * np + gp];
-    v.s0[c] = hist ? P[(P_X0S + c) * np + gp] : R(0);
+    for (int c = 0; c < 6; ++c) {
+      v.s1[c] = P[(P_X1S + c) * np + gp];
+      v.s2[c] = P[(P_X2S + c) * np + gp];
+      v.s0[c] = hist ? P[(P_X0S + c) * np + gp] : R(0);
+    }
   }
 }
 
-// Phase 1 for one node: W and T from its register values.
-template <typename R, bool ADJ, int NB>
-__device__ __forceinline__ void pml_node_fields(const PmlNode<R>& v, const R Le[3], const R Lp[3], const R Lw[3],
-                                                R la, R m, int n, R (&sW)[9][NB], R (&sT)[9][NB]) {
+// Phase 1 for one node: W (U) from the displacements.
+template <typename R, int NB>
+__device__ __forceinline__ void pml_node_w(const PmlNode<R>& v, const R Le[3], const R Lp[3], const R Lw[3], int n,
+                                           R (&sW)[9][NB]) {
 #pragma unroll
   for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii) sW[3 * kk + ii][n] = Le[kk] * v.u2[ii] + Lp[kk] * v.u1[ii] + Lw[kk] * v.u0[ii];
+}
+
+// Phase 1 for one node: T from the stresses.
+template <typename R, bool ADJ, int NB>
+__device__ __forceinline__ void pml_node_t(const PmlNode<R>& v, const R Le[3], const R Lp[3], const R Lw[3], R la,
+                                           R m, int n, R (&sT)[9][NB]) {
   if constexpr (!ADJ) {
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii)
@@ -391,13 +433,11 @@ __device__ __forceinline__ void pml_node_fields(const PmlNode<R>& v, const R Le[
 }
 
 // Q (6 values) at LGL point q of the tile's bricks; false for points of bricks
-// outside a ragged tile.
+// outside a ragged tile.  sLam, sMu: box-node materials (forward only).
 template <typename R, int TX, int TY, int TZ, bool ADJ>
 __device__ __forceinline__ bool pml_point_value(const Geo& g, int cx, int cy, int cz, int q,
-                                                const R* __restrict__ sW,
-                                                const R (&sLam)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
-                                                const R (&sMu)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
-                                                R Q[6]) {
+                                                const R* __restrict__ sW, const R* __restrict__ sLam,
+                                                const R* __restrict__ sMu, R Q[6]) {
   constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, NB = BX * BY * (2 * TZ + 1);
   const R s2h = R(2.0 / g.h);
   const int pt = q % 27, e = q / 27;
@@ -439,100 +479,87 @@ __device__ __forceinline__ bool pml_point_value(const Geo& g, int cx, int cy, in
   return true;
 }
 
-// Phase 2: Q at every LGL point of the tile's bricks.
-template <typename R, int TX, int TY, int TZ, bool ADJ>
-__device__ __forceinline__ void pml_points(const Geo& g, int cx, int cy, int cz,
-                                           const R (&sW)[9][(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
-                                           const R (&sLam)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
-                                           const R (&sMu)[(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
-                                           R (&sQ)[6][27 * TX * TY * TZ]) {
-  constexpr int NP = 27 * TX * TY * TZ;
-  for (int q = threadIdx.x; q < NP; q += blockDim.x) {
-    R Q[6];
-    if (!pml_point_value<R, TX, TY, TZ, ADJ>(g, cx, cy, cz, q, &sW[0][0], sLam, sMu, Q)) continue;
+// Along one axis, the u-row term of local node l (0 <= l <= 2 cnt) is
+// sum_k c[k] T(l - 2 + k): over the tile's bricks containing l, the LGL weight
+// of point a times the derivative of the node's basis function at a, placed
+// at the box node of a.  Brick below (l odd: position 1, else 2) and brick
+// above (l even: position 0) give
+//   l odd:   (0, 2/3, 0, -2/3, 0)
+//   l even:  below (-1/6, 2/3, 1/2, 0, 0) + above (0, 0, -1/2, -2/3, 1/6).
+// S: the sum of the 1D weights of those bricks at l.  Indices are clamped
+// to the tile box (the clamped reads have coefficient 0).
+template <typename R>
+__device__ __forceinline__ void axis_stencil(int l, int cnt, R c[5], int o[5], R& S) {
+  const bool odd = l & 1, lo = l >= 1, hi = !odd && (l >> 1) < cnt;
+  const R third = R(1.0 / 3.0), sixth = R(1.0 / 6.0), two3 = R(2.0 / 3.0);
+  c[0] = (!odd && lo) ? -sixth : R(0);
+  c[1] = lo ? two3 : R(0);
+  c[2] = odd ? R(0) : R(lo ? 0.5 : 0.0) - R(hi ? 0.5 : 0.0);
+  c[3] = (odd || hi) ? -two3 : R(0);
+  c[4] = hi ? sixth : R(0);
+  S = odd ? R(4.0 / 3.0) : R(lo ? third : R(0)) + R(hi ? third : R(0));
 #pragma unroll
-    for (int v = 0; v < 6; ++v) sQ[v][q] = Q[v];
-  }
+  for (int k = 0; k < 5; ++k) o[k] = min(max(l - 2 + k, 0), 2 * cnt);
 }
 
-// Phase 3 for one box node (local lx, ly, lz): u-rows and S-rows, stored.
+// Phase 3, u-rows of box node (lx, ly, lz) from the nodal T.
 template <typename R, int TX, int TY, int TZ>
-__device__ __forceinline__ void pml_node_rows(const Geo& g, const Tile& t, int cx, int cy, int cz, int lx, int ly,
-                                              int lz, const R (&sT)[9][(2 * TX + 1) * (2 * TY + 1) * (2 * TZ + 1)],
-                                              const R (&sQ)[6][27 * TX * TY * TZ], R* __restrict__ res,
-                                              const Part& PT) {
-  constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1;
-  const R s2h = R(2.0 / g.h);
-  const R vol = R(0.125 * g.h * g.h * g.h);
-  const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
-  const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
-  const size_t gp = (size_t)pml_index(g, gi, gj, gk);
-  int exs[2], pxs[2], eys[2], pys[2], ezs[2], pzs[2];
-  const int nex = node_bricks(lx, cx, exs, pxs);
-  const int ney = node_bricks(ly, cy, eys, pys);
-  const int nez = node_bricks(lz, cz, ezs, pzs);
-  // 1D weight sums of the tile's bricks that contain the node
-  const R Sx = R(wlgl(pxs[0]) + (nex > 1 ? wlgl(pxs[1]) : 0.0));
-  const R Sy = R(wlgl(pys[0]) + (ney > 1 ? wlgl(pys[1]) : 0.0));
-  const R Sz = R(wlgl(pzs[0]) + (nez > 1 ? wlgl(pzs[1]) : 0.0));
-  // u-rows: the stress-like tensor is nodal, so each direction factorizes
+__device__ __forceinline__ void pml_u_rows(const Geo& g, int cx, int cy, int cz, int lx, int ly, int lz,
+                                           const R* __restrict__ sT, R out[3]) {
+  constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, NB = BX * BY * (2 * TZ + 1);
+  R c[5], Sx, Sy, Sz;
+  int o[5];
   R dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0}, dz[3] = {0, 0, 0};
+  axis_stencil<R>(lx, cx, c, o, Sx);
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    if (b >= nex) break;
+  for (int k = 0; k < 5; ++k) {
+    const int n = o[k] + BX * (ly + BY * lz);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const R cf = R(dlgl(a, pxs[b]) * wlgl(a));
-      const int nx = (2 * exs[b] + a) + BX * (ly + BY * lz);
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) dx[ii] += cf * sT[3 * ii + 0][nx];
-    }
+    for (int ii = 0; ii < 3; ++ii) dx[ii] += c[k] * sT[(3 * ii + 0) * NB + n];
   }
+  axis_stencil<R>(ly, cy, c, o, Sy);
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    if (b >= ney) break;
+  for (int k = 0; k < 5; ++k) {
+    const int n = lx + BX * (o[k] + BY * lz);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const R cf = R(dlgl(a, pys[b]) * wlgl(a));
-      const int ny = lx + BX * ((2 * eys[b] + a) + BY * lz);
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) dy[ii] += cf * sT[3 * ii + 1][ny];
-    }
+    for (int ii = 0; ii < 3; ++ii) dy[ii] += c[k] * sT[(3 * ii + 1) * NB + n];
   }
+  axis_stencil<R>(lz, cz, c, o, Sz);
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    if (b >= nez) break;
+  for (int k = 0; k < 5; ++k) {
+    const int n = lx + BX * (ly + BY * o[k]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const R cf = R(dlgl(a, pzs[b]) * wlgl(a));
-      const int nz = lx + BX * (ly + BY * (2 * ezs[b] + a));
-#pragma unroll
-      for (int ii = 0; ii < 3; ++ii) dz[ii] += cf * sT[3 * ii + 2][nz];
-    }
+    for (int ii = 0; ii < 3; ++ii) dz[ii] += c[k] * sT[(3 * ii + 2) * NB + n];
   }
-  // S-rows: sum of the point values of every tile brick containing the node
-  R q6[6] = {0, 0, 0, 0, 0, 0};
+  const R f = R(0.125 * g.h * g.h * g.h) * R(2.0 / g.h);
+#pragma unroll
+  for (int ii = 0; ii < 3; ++ii) out[ii] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
+}
+
+// Phase 3, S-rows of box node (lx, ly, lz): the sum of the point values of
+// every tile brick containing the node.
+template <typename R, int TX, int TY, int TZ>
+__device__ __forceinline__ void pml_s_rows(int cx, int cy, int cz, int lx, int ly, int lz,
+                                           const R* __restrict__ sQ, R q6[6]) {
+  constexpr int NP = 27 * TX * TY * TZ;
+  int ox[2], oy[2], oz[2];
+  bool vx[2], vy[2], vz[2];
+  axis_bricks(lx, cx, 27, 1, ox, vx);
+  axis_bricks(ly, cy, 27 * TX, 3, oy, vy);
+  axis_bricks(lz, cz, 27 * TX * TY, 9, oz, vz);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) q6[v] = 0;
 #pragma unroll
   for (int a3 = 0; a3 < 2; ++a3)
 #pragma unroll
     for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
       for (int a1 = 0; a1 < 2; ++a1) {
-        if (a1 >= nex || a2 >= ney || a3 >= nez) continue;
-        const int qn = 27 * (exs[a1] + TX * (eys[a2] + TY * ezs[a3])) + pxs[a1] + 3 * pys[a2] + 9 * pzs[a3];
+        if (!(vx[a1] && vy[a2] && vz[a3])) continue;
+        const int qn = ox[a1] + oy[a2] + oz[a3];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) q6[v] += sQ[v][qn];
+        for (int v = 0; v < 6; ++v) q6[v] += sQ[v * NP + qn];
       }
-  const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
-  const RowAddr ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
-#pragma unroll
-  for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
-  if (!is_dirichlet(g, gi, gj, gk)) {
-    const R f = vol * s2h;
-#pragma unroll
-    for (int ii = 0; ii < 3; ++ii)
-      res[ra.u + ii * ra.us] = f * (Sy * Sz * dx[ii] + Sx * Sz * dy[ii] + Sx * Sy * dz[ii]);
-  }
 }
 
 // Per-node constants of phase 1: PML coefficients, history flag, indices.
@@ -541,29 +568,33 @@ __device__ __forceinline__ void pml_node_setup(const Geo& g, int gi, int gj, int
                                                bool& hist, size_t& gnode, size_t& gp) {
   gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
   gp = (size_t)pml_index(g, gi, gj, gk);
-  const PmlCoef c = pml_coef_tab(g, gi, gj, gk);
-  hist = c.nbeta >= 2;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    Le[d] = R(c.Le[d]);
-    Lp[d] = R(c.Lp[d]);
-    Lw[d] = R(c.Lw[d]);
-  }
+  // products of the 1D stretching factors in the state precision
+  const int nt = ax_n(g);
+  const double* A = g.tab;
+  const double* B = g.tab + nt;
+  const R ax = R(A[gi]), ay = R(A[ax_y(g) + gj]), az = R(A[ax_z(g) + gk]);
+  const R bx = R(B[gi]), by = R(B[ax_y(g) + gj]), bz = R(B[ax_z(g) + gk]);
+  hist = (B[gi] > 0.0) + (B[ax_y(g) + gj] > 0.0) + (B[ax_z(g) + gk] > 0.0) >= 2;   // as the layout decides
+  Le[0] = ay * az; Lp[0] = ay * bz + by * az; Lw[0] = by * bz;
+  Le[1] = ax * az; Lp[1] = ax * bz + bx * az; Lw[1] = bx * bz;
+  Le[2] = ax * ay; Lp[2] = ax * by + bx * ay; Lw[2] = bx * by;
 }
 
 // One workgroup per (tile, source) (SRCLOOP = false) or per tile with the
-// sources in turn (SRCLOOP = true).
-template <typename R, int TX, int TY, int TZ, bool ADJ, bool SRCLOOP>
+// sources in turn (SRCLOOP = true); PART selects the rows (see above).
+template <typename R, int TX, int TY, int TZ, bool ADJ, bool SRCLOOP, int PART>
 __global__ void __launch_bounds__(PMLFWI_ETHREADS)
 pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
                    const R* __restrict__ Ybase, long long ystride, const R* __restrict__ lam,
                    const R* __restrict__ mu, R* __restrict__ rbase, Part PT) {
   constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
   constexpr int NB = BX * BY * BZ, NP = 27 * TX * TY * TZ;
-  __shared__ R sW[9][NB];   // [3k + i]: Le_kk u'_i + Lp_kk u_i + Lw_kk ubar_i
-  __shared__ R sQ[6][NP];
-  __shared__ R sT[9][NB];   // [3i + k]: nodal stress-like tensor of the u-rows
-  __shared__ R sLam[NB], sMu[NB];
+  constexpr bool DS = PART & PML_SROWS, DU = PART & PML_UROWS;
+  constexpr bool MAT = (DS && !ADJ) || (DU && ADJ);   // materials: forward Q, transposed T
+  __shared__ R sW[DS ? 9 : 1][DS ? NB : 1];   // [3k + i]: Le_kk u'_i + Lp_kk u_i + Lw_kk ubar_i
+  __shared__ R sQ[DS ? 6 : 1][DS ? NP : 1];
+  __shared__ R sT[DU ? 9 : 1][DU ? NB : 1];   // [3i + k]: nodal stress-like tensor of the u-rows
+  __shared__ R sLam[MAT ? NB : 1], sMu[MAT ? NB : 1];
 
   const int ti = xcd_tile();
   if (ti >= ntiles) return;
@@ -572,14 +603,16 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
   const size_t nn = (size_t)g.sn, np = (size_t)g.sp;
 
-  for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-    const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-    if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-    const int mi = material_index(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz);
-    sLam[n] = lam[mi];
-    sMu[n] = mu[mi];
+  if constexpr (MAT) {
+    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
+      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
+      const int mi = material_index(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz);
+      sLam[n] = lam[mi];
+      sMu[n] = mu[mi];
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   const int src0 = SRCLOOP ? 0 : (int)blockIdx.y, src1 = SRCLOOP ? nsrc : src0 + 1;
   for (int src = src0; src < src1; ++src) {
@@ -592,19 +625,45 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
       size_t gnode, gp;
       pml_node_setup<R>(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz, Le, Lp, Lw, hist, gnode, gp);
       PmlNode<R> v;
-      pml_load_node<R>(Y, nn, np, gnode, gp, hist, v);
-      pml_node_fields<R, ADJ, NB>(v, Le, Lp, Lw, sLam[n], sMu[n], n, sW, sT);
+      pml_load_node<R, DS, DU>(Y, nn, np, gnode, gp, hist, v);
+      if constexpr (DS) pml_node_w<R, NB>(v, Le, Lp, Lw, n, sW);
+      if constexpr (DU) pml_node_t<R, ADJ, NB>(v, Le, Lp, Lw, MAT ? sLam[n] : R(0), MAT ? sMu[n] : R(0), n, sT);
     }
     __syncthreads();
-    pml_points<R, TX, TY, TZ, ADJ>(g, cx, cy, cz, sW, sLam, sMu, sQ);
-    __syncthreads();
+    if constexpr (DS) {
+      for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+        R Q[6];
+        if (!pml_point_value<R, TX, TY, TZ, ADJ>(g, cx, cy, cz, q, &sW[0][0], &sLam[0], &sMu[0], Q)) continue;
+#pragma unroll
+        for (int v = 0; v < 6; ++v) sQ[v][q] = Q[v];
+      }
+      __syncthreads();
+    }
     R* res = rbase + (size_t)src * PT.per_src;
     for (int n = threadIdx.x; n < NB; n += blockDim.x) {
       const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
       if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      pml_node_rows<R, TX, TY, TZ>(g, t, cx, cy, cz, lx, ly, lz, sT, sQ, res, PT);
+      const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
+      const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
+      const size_t gp = (size_t)pml_index(g, gi, gj, gk);
+      const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+      const RowAddr ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
+      if constexpr (DS) {
+        R q6[6];
+        pml_s_rows<R, TX, TY, TZ>(cx, cy, cz, lx, ly, lz, &sQ[0][0], q6);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
+      }
+      if constexpr (DU) {
+        if (!is_dirichlet(g, gi, gj, gk)) {
+          R u3[3];
+          pml_u_rows<R, TX, TY, TZ>(g, cx, cy, cz, lx, ly, lz, &sT[0][0], u3);
+#pragma unroll
+          for (int ii = 0; ii < 3; ++ii) res[ra.u + ii * ra.us] = u3[ii];
+        }
+      }
     }
-    __syncthreads();
+    if constexpr (SRCLOOP) __syncthreads();
   }
 }
 

@@ -1,5 +1,5 @@
 // C ABI of the MI355X hot path: plan, workspace layout, forward / misfit /
-// adjoint-gradient drivers.  See include/pmlfwi.h for the contract.
+// adjoint-gradient step loops.  See include/pmlfwi.h for the contract.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -90,6 +90,15 @@ namespace {
 #define PMLFWI_TX 4
 #define PMLFWI_TY 2
 #define PMLFWI_TZ 2
+#endif
+// PML operator as two launches, one per row type (smaller LDS and register
+// footprints, 8 waves per SIMD; they interleave with the interior launch on
+// the other stream), u-rows first, rather than one launch for both.
+#ifndef PMLFWI_PML_SPLIT
+#define PMLFWI_PML_SPLIT 1
+#endif
+#ifndef PMLFWI_SPLIT_FIRST
+#define PMLFWI_SPLIT_FIRST PML_UROWS
 #endif
 #ifndef PMLFWI_CONCURRENT
 #define PMLFWI_CONCURRENT 1
@@ -564,7 +573,7 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
 
 inline unsigned blocks(size_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// ---------------------------------------------------------------- driver
+// ---------------------------------------------------------------- step loops
 template <typename R>
 struct Run {
   fwi_plan* p;
@@ -622,6 +631,16 @@ struct Run {
   // The interior and PML bricks write disjoint partial-array entries, so the
   // two launches may run at the same time: the interior one goes to the plan's
   // second stream when both lists are non-empty.
+  template <int PART>
+  void launch_pml(bool adj, dim3 grid, int nt, const R* Y, long long reg) {
+    if (adj)
+      pml_element_kernel<R, TX, TY, TZ, true, SRCLOOP, PART><<<grid, ETHREADS, 0, st>>>(
+          g(), p->d_tiles_pml, nt, p->nsrc, Y, reg, lam(), mu(), res(), L.part);
+    else
+      pml_element_kernel<R, TX, TY, TZ, false, SRCLOOP, PART><<<grid, ETHREADS, 0, st>>>(
+          g(), p->d_tiles_pml, nt, p->nsrc, Y, reg, lam(), mu(), res(), L.part);
+  }
+
   fwi_status elements(bool adj, const R* Y, const R* fwd, double gw, bool interior_only = false) {
     const Geo& G = g();
     const long long reg = (long long)L.reg_elems;
@@ -655,12 +674,12 @@ struct Run {
       const int nt = (int)p->tiles_pml.size();
       const dim3 grid(8u * (unsigned)((nt + 7) / 8), SRCLOOP ? 1 : ns);
       TimedLaunch tl(p, adj ? FWI_K_PML_ADJ : FWI_K_PML, st);
-      if (adj)
-        pml_element_kernel<R, TX, TY, TZ, true, SRCLOOP><<<grid, ETHREADS, 0, st>>>(G, p->d_tiles_pml, nt, ns, Y, reg,
-                                                                                    lam(), mu(), res(), L.part);
-      else
-        pml_element_kernel<R, TX, TY, TZ, false, SRCLOOP><<<grid, ETHREADS, 0, st>>>(G, p->d_tiles_pml, nt, ns, Y, reg,
-                                                                                     lam(), mu(), res(), L.part);
+      if (PMLFWI_PML_SPLIT) {
+        launch_pml<PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg);
+        launch_pml<PML_ALL ^ PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg);
+      } else {
+        launch_pml<PML_ALL>(adj, grid, nt, Y, reg);
+      }
     }
     if (fork) HIP_TRY(p, hipStreamWaitEvent(st, p->join_ev, 0));
     HIP_TRY(p, hipGetLastError());

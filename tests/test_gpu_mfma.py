@@ -3,7 +3,7 @@
 The dense reference-matrix form must give the operator of the scalar
 kernels: one application against the FP64 oracle at FP32 rounding level
 (ragged tiles, several sources), then forward, misfit and gradient against
-the oracle at the benchmark spec's tolerances (traces 1e-5, gradients 1e-4), on
+the oracle at the FP32 tolerances (traces 1e-5, gradients 1e-4), on
 the 864-brick workload and, for 3 steps, on the 62,500-brick mesh.
 """
 import numpy as np

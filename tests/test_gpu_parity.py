@@ -77,7 +77,7 @@ def test_forward_adjoint_gradient_fp64(P, name, ckpt):
 
 
 def test_config1_full_fp64_and_fp32(P):
-    """8x8x4 m interior, 400 RK4 steps: the benchmark spec's tolerances in FP32."""
+    """8x8x4 m interior, 400 RK4 steps: FP64 and the FP32 tolerances (traces 1e-5, gradients 1e-4)."""
     import torch
     name = "cfg1"
     wl = workload(name)
