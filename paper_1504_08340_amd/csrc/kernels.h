@@ -176,18 +176,23 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
   __shared__ R sG[GRAD ? 2 : 1][GRAD ? NP : 1];
   __shared__ double sGacc[GRAD ? 2 : 1][GRAD ? NB : 1];   // summed over sources
 
+  static_assert(NB <= PMLFWI_ETHREADS, "one box node per thread");
   const int ti = xcd_tile();
   if (ti >= ntiles) return;
   const Tile t = tiles[ti];
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
-  const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
   const size_t nn = (size_t)g.sn;
   const R s2h = R(2.0 / g.h);
 
-  for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-    const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-    if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-    const int mi = interior_index(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz);
+  // this thread's box node and its constants, shared by the sources
+  const int n = threadIdx.x;
+  const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+  const bool live = n < NB && lx <= 2 * cx && ly <= 2 * cy && lz <= 2 * cz;
+  const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
+  const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
+  const int mi = live ? interior_index(g, i, j, k) : 0;
+  const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+  if (live) {
     sLam[n] = lam[mi];
     sMu[n] = mu[mi];
     if constexpr (GRAD) {
@@ -200,16 +205,11 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
   const int src0 = SRCLOOP ? 0 : (int)blockIdx.y, src1 = SRCLOOP ? nsrc : src0 + 1;
   for (int src = src0; src < src1; ++src) {
     const R* Yu = Ybase + (size_t)src * ystride;
-    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-      const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
+    if (live) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) sU[d][n] = Yu[d * nn + node];
       if constexpr (GRAD) {
         const R* F = fwd + (size_t)src * fstride;
-        const int mi = interior_index(g, i, j, k);
 #pragma unroll
         for (int d = 0; d < 3; ++d) sV[d][n] = F[(size_t)d * g.si + mi];
       }
@@ -221,8 +221,8 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
       const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
       if (ea >= cx || eb >= cy || ec >= cz) continue;
       const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
-      const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
-      const int nq = lx + BX * (ly + BY * lz);
+      const int px = 2 * ea + qa, py = 2 * eb + qb, pz = 2 * ec + qc;   // box node of the point
+      const int nq = px + BX * (py + BY * pz);
       R G[3][3], Gf[3][3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -230,9 +230,9 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const R cxa = R(dlgl(qa, a)), cya = R(dlgl(qb, a)), cza = R(dlgl(qc, a));
-          const int nx = (2 * ea + a) + BX * (ly + BY * lz);
-          const int ny = lx + BX * ((2 * eb + a) + BY * lz);
-          const int nz = lx + BX * (ly + BY * (2 * ec + a));
+          const int nx = (2 * ea + a) + BX * (py + BY * pz);
+          const int ny = px + BX * ((2 * eb + a) + BY * pz);
+          const int nz = px + BX * (py + BY * (2 * ec + a));
           gx += cxa * sU[d][nx];
           gy += cya * sU[d][ny];
           gz += cza * sU[d][nz];
@@ -291,10 +291,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
     __syncthreads();
 
     R* res = rbase + (size_t)src * PT.per_src;
-    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
+    if (live) {
       int ox[2], oy[2], oz[2];
       bool vx[2], vy[2], vz[2];
       axis_bricks(lx, cx, 27, 1, ox, vx);
@@ -318,10 +315,8 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
               gm += sG[1][qn];
             }
           }
-      const int c = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
       if (!is_dirichlet(g, i, j, k)) {
-        const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
-        const RowAddr ra = row_addr(g, PT, c, i, j, k, node, 0);
+        const RowAddr ra = row_addr(g, PT, cs, i, j, k, node, 0);
         res[ra.u] = r0 * s2h;
         res[ra.u + ra.us] = r1 * s2h;
         res[ra.u + 2 * ra.us] = r2 * s2h;
@@ -334,12 +329,8 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
     __syncthreads();
   }
   if constexpr (GRAD) {
-    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int i = 2 * t.x + lx, j = 2 * t.y + ly, k = 2 * t.z + lz;
-      const int c = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
-      const size_t o = (size_t)PG.off[c] + part_node(g, PG, c, i, j, k), gs = (size_t)PG.size[c];
+    if (live) {
+      const size_t o = (size_t)PG.off[cs] + part_node(g, PG, cs, i, j, k), gs = (size_t)PG.size[cs];
       const double a0 = gacc[o], a1 = gacc[o + gs];
       gacc[o] = a0 + gw * sGacc[0][n];
       gacc[o + gs] = a1 + gw * sGacc[1][n];
@@ -590,44 +581,52 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
   constexpr int NB = BX * BY * BZ, NP = 27 * TX * TY * TZ;
   constexpr bool DS = PART & PML_SROWS, DU = PART & PML_UROWS;
-  constexpr bool MAT = (DS && !ADJ) || (DU && ADJ);   // materials: forward Q, transposed T
+  constexpr bool MATQ = DS && !ADJ;   // box-node materials in LDS for the forward Q
+  static_assert(NB <= PMLFWI_ETHREADS, "one box node per thread");
   __shared__ R sW[DS ? 9 : 1][DS ? NB : 1];   // [3k + i]: Le_kk u'_i + Lp_kk u_i + Lw_kk ubar_i
   __shared__ R sQ[DS ? 6 : 1][DS ? NP : 1];
   __shared__ R sT[DU ? 9 : 1][DU ? NB : 1];   // [3i + k]: nodal stress-like tensor of the u-rows
-  __shared__ R sLam[MAT ? NB : 1], sMu[MAT ? NB : 1];
+  __shared__ R sLam[MATQ ? NB : 1], sMu[MATQ ? NB : 1];
 
   const int ti = xcd_tile();
   if (ti >= ntiles) return;
   const Tile t = tiles[ti];
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
-  const int nbx = 2 * cx + 1, nby = 2 * cy + 1, nbz = 2 * cz + 1;
   const size_t nn = (size_t)g.sn, np = (size_t)g.sp;
 
-  if constexpr (MAT) {
-    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int mi = material_index(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz);
-      sLam[n] = lam[mi];
-      sMu[n] = mu[mi];
+  // this thread's box node and its constants, shared by the sources
+  const int n = threadIdx.x;
+  const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+  const bool live = n < NB && lx <= 2 * cx && ly <= 2 * cy && lz <= 2 * cz;
+  const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
+  R Le[3] = {0, 0, 0}, Lp[3] = {0, 0, 0}, Lw[3] = {0, 0, 0}, la = 0, m = 0;
+  bool hist = false, free_u = false;
+  size_t gnode = 0, gp = 0;
+  RowAddr ra{};
+  if (live) {
+    pml_node_setup<R>(g, gi, gj, gk, Le, Lp, Lw, hist, gnode, gp);
+    const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+    ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
+    free_u = !is_dirichlet(g, gi, gj, gk);
+    if constexpr (MATQ || (DU && ADJ)) {
+      const int mi = material_index(g, gi, gj, gk);
+      la = lam[mi];
+      m = mu[mi];
+      if constexpr (MATQ) {
+        sLam[n] = la;
+        sMu[n] = m;
+      }
     }
-    __syncthreads();
   }
 
   const int src0 = SRCLOOP ? 0 : (int)blockIdx.y, src1 = SRCLOOP ? nsrc : src0 + 1;
   for (int src = src0; src < src1; ++src) {
     const R* Y = Ybase + (size_t)src * ystride;
-    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      R Le[3], Lp[3], Lw[3];
-      bool hist;
-      size_t gnode, gp;
-      pml_node_setup<R>(g, 2 * t.x + lx, 2 * t.y + ly, 2 * t.z + lz, Le, Lp, Lw, hist, gnode, gp);
+    if (live) {
       PmlNode<R> v;
       pml_load_node<R, DS, DU>(Y, nn, np, gnode, gp, hist, v);
       if constexpr (DS) pml_node_w<R, NB>(v, Le, Lp, Lw, n, sW);
-      if constexpr (DU) pml_node_t<R, ADJ, NB>(v, Le, Lp, Lw, MAT ? sLam[n] : R(0), MAT ? sMu[n] : R(0), n, sT);
+      if constexpr (DU) pml_node_t<R, ADJ, NB>(v, Le, Lp, Lw, la, m, n, sT);
     }
     __syncthreads();
     if constexpr (DS) {
@@ -640,14 +639,7 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
       __syncthreads();
     }
     R* res = rbase + (size_t)src * PT.per_src;
-    for (int n = threadIdx.x; n < NB; n += blockDim.x) {
-      const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
-      if (lx >= nbx || ly >= nby || lz >= nbz) continue;
-      const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
-      const size_t gnode = (size_t)gi + (size_t)g.NX * (gj + (size_t)g.NY * gk);
-      const size_t gp = (size_t)pml_index(g, gi, gj, gk);
-      const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
-      const RowAddr ra = row_addr(g, PT, cs, gi, gj, gk, gnode, gp);
+    if (live) {
       if constexpr (DS) {
         R q6[6];
         pml_s_rows<R, TX, TY, TZ>(cx, cy, cz, lx, ly, lz, &sQ[0][0], q6);
@@ -655,7 +647,7 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
         for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
       }
       if constexpr (DU) {
-        if (!is_dirichlet(g, gi, gj, gk)) {
+        if (free_u) {
           R u3[3];
           pml_u_rows<R, TX, TY, TZ>(g, cx, cy, cz, lx, ly, lz, &sT[0][0], u3);
 #pragma unroll
@@ -690,6 +682,8 @@ struct NodalArgs {
   int wav_len, wav_idx;
   R* store;                   // x1 displacement of the produced register on the
   long long store_stride;     // interior closure (per source stride), or nullptr
+  long long first, last;      // row range of this launch: [0, sn) node rows, then PML rows
+  unsigned rot;               // workgroup b takes rows of block (b + rot) mod grid
 };
 
 // Where a node's contributions sit in the partial arrays: array 0 always, and
@@ -745,7 +739,9 @@ __device__ __forceinline__ R gather_rows(const Part& P, const PartSlots& S, cons
 template <typename R, int MODE, bool STORE>
 __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned blk = A.rot ? (blockIdx.x + A.rot) % gridDim.x : blockIdx.x;
+  const long long gid = A.first + (long long)blk * blockDim.x + threadIdx.x;
+  if (gid >= A.last) return;
   const size_t nn = (size_t)g.sn, np = (size_t)g.sp;
   const R* __restrict__ Y = A.Yin + (size_t)src * A.reg;
   R* __restrict__ Yo = MODE == 2 ? nullptr : A.Yout + (size_t)src * A.reg;

@@ -97,6 +97,11 @@ namespace {
 #ifndef PMLFWI_PML_SPLIT
 #define PMLFWI_PML_SPLIT 1
 #endif
+// Nodal launch: 0 one grid, 1 one grid with the (heavier) PML-row blocks
+// dispatched first, 2 node rows and PML rows as two launches.
+#ifndef PMLFWI_NODAL_ORDER
+#define PMLFWI_NODAL_ORDER 1
+#endif
 #ifndef PMLFWI_SPLIT_FIRST
 #define PMLFWI_SPLIT_FIRST PML_UROWS
 #endif
@@ -703,13 +708,26 @@ struct Run {
       A.wav_len = 2 * p->prob.nsteps + 1; A.wav_idx = 2 * step + toff[s];
     }
     A.store = store; A.store_stride = 3LL * G.si;
-    dim3 grid(blocks((size_t)G.sn + G.n_pml, 256), p->nsrc);
+    const long long rows = (long long)G.sn + G.n_pml;
     {
       TimedLaunch tl(p, FWI_K_NODAL, st);
       auto kern = A.mode == 0 ? (store ? nodal_rk_kernel<R, 0, true> : nodal_rk_kernel<R, 0, false>)
                 : A.mode == 1 ? (store ? nodal_rk_kernel<R, 1, true> : nodal_rk_kernel<R, 1, false>)
                               : (store ? nodal_rk_kernel<R, 2, true> : nodal_rk_kernel<R, 2, false>);
-      kern<<<grid, 256, 0, st>>>(G, A);
+      if (PMLFWI_NODAL_ORDER == 2) {
+        A.first = 0;
+        A.last = G.sn;
+        kern<<<dim3(blocks((size_t)G.sn, 256), p->nsrc), 256, 0, st>>>(G, A);
+        A.first = G.sn;
+        A.last = rows;
+        kern<<<dim3(blocks((size_t)G.n_pml, 256), p->nsrc), 256, 0, st>>>(G, A);
+      } else {
+        const unsigned nb = (unsigned)blocks((size_t)rows, 256);
+        A.first = 0;
+        A.last = rows;
+        A.rot = PMLFWI_NODAL_ORDER == 1 ? (unsigned)(G.sn / 256) % nb : 0u;
+        kern<<<dim3(nb, p->nsrc), 256, 0, st>>>(G, A);
+      }
     }
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
