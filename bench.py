@@ -38,13 +38,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 MFMA_PEAK_TFLOPS = {"fp32-mfma": 157.3, "fp32-bf16x3": 2500.0}   # dense, published
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32-mfma": 2, "fp32-bf16x3": 3}
-# Matrix-core work of one interior workgroup (a 4x2x2 brick tile, one source):
-# G = B U with B 81x27 padded to 96 rows, U 27x48; R = B^T S with 27 rows
-# padded to 32, K = 81.  FP32 16x16x4 MFMA: 18 tiles x 7 steps + 6 tiles x 21
-# steps; split BF16 16x16x16: 18 x 2 + 6 x 6 steps, 3 products each.
-MFMA_FLOPS_PER_TILE = {"fp32-mfma": (18 * 7 + 6 * 21) * 2 * 16 * 16 * 4,
-                       "fp32-bf16x3": (18 * 2 + 6 * 6) * 3 * 2 * 16 * 16 * 16}
-USEFUL_FLOPS_PER_TILE = 2 * (2 * 81 * 27 * 48)
+# Matrix-core work of one interior workgroup (one brick tile of NE bricks, one
+# source): G = B U with B 81x27 padded to 96 rows and U 27 x 3NE; R = B^T S with
+# 27 rows padded to 32, K = 81; NT = ceil(3NE / 16) column tiles.  FP32 16x16x4
+# MFMA: 6 NT tiles x 7 steps + 2 NT tiles x 21 steps; split BF16 16x16x16:
+# 6 NT x 2 + 2 NT x 6 steps, 3 products each.
+
+
+def mfma_flops_per_tile(precision, ne):
+    nt = -(-3 * ne // 16)
+    if precision == "fp32-mfma":
+        return (6 * nt * 7 + 2 * nt * 21) * 2 * 16 * 16 * 4
+    return (6 * nt * 2 + 2 * nt * 6) * 3 * 2 * 16 * 16 * 16
+
+
+def useful_flops_per_tile(ne):
+    return 2 * (2 * 81 * 27 * 3 * ne)
+
+
 CSRC = os.path.join(ROOT, "paper_1504_08340_amd", "csrc")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic__kernels__cfg40x40x20_4src_fp32.md")
 
@@ -222,13 +233,13 @@ def main():
 
     mfma = None
     if args.precision in MFMA_PEAK_TFLOPS and "interior" in kstats:
-        ex, ey, ez = prob.ne_int
-        tiles = -(-ex // 4) * -(-ey // 2) * -(-ez // 2)
+        tiles = S.sizes.tiles_interior
+        ne = S.sizes.tile[0] * S.sizes.tile[1] * S.sizes.tile[2]
         t = kstats["interior"]["mean_ms"] * 1e-3
-        executed = tiles * wl.nsrc * MFMA_FLOPS_PER_TILE[args.precision] / t / 1e12
+        executed = tiles * wl.nsrc * mfma_flops_per_tile(args.precision, ne) / t / 1e12
         mfma = {"kernel": "interior", "executed_tflops": executed, "peak": MFMA_PEAK_TFLOPS[args.precision],
                 "unit": "TFLOP/s", "frac": executed / MFMA_PEAK_TFLOPS[args.precision],
-                "useful_tflops": tiles * wl.nsrc * USEFUL_FLOPS_PER_TILE / t / 1e12,
+                "useful_tflops": tiles * wl.nsrc * useful_flops_per_tile(ne) / t / 1e12,
                 "mean_launch_us": kstats["interior"]["mean_ms"] * 1e3}
     line = {
         "metric": "RK4 DOF-steps/s fwd+adj",

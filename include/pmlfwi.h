@@ -110,6 +110,10 @@ typedef struct {
   int64_t trace_len;      /* nsrc*(nsteps+1)*nrec*3 */
   int64_t workspace_bytes;
   int64_t register_bytes; /* one stored state (all sources) */
+  int64_t tile[3];        /* bricks per element tile along x, y, z (build constants) */
+  int64_t tiles_interior; /* element tiles over the interior bricks (ragged ones included) */
+  int64_t tiles_pml;      /* element tiles over the PML bricks */
+  int64_t element_threads;/* threads of an element-kernel workgroup */
 } fwi_sizes;
 
 typedef struct fwi_plan fwi_plan;

@@ -50,7 +50,8 @@ class fwi_problem(ctypes.Structure):
 class fwi_sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_nodes", "n_int_nodes", "n_pml_nodes", "n_state", "n_hist", "trace_len",
-        "workspace_bytes", "register_bytes")]
+        "workspace_bytes", "register_bytes")] + [("tile", ctypes.c_int64 * 3)] + [
+        (n, ctypes.c_int64) for n in ("tiles_interior", "tiles_pml", "element_threads")]
 
 
 _P = ctypes.c_void_p

@@ -13,10 +13,13 @@
 //   21 x n_pml [x0 u (3) | x0 S (6) | x1 S (6) | x2 S (6)] on the PML shell.
 //   Stress order (xx, yy, zz, yz, xz, xy).
 //
-// Element work is done per tile of bricks (a workgroup per tile, all sources
-// in turn).  Scatter without atomics: a node lies on the upper face (local
-// index 2*count) of at most one tile per axis, so the set c of axes on which
-// it is an upper-face node differs for every tile containing it.  A tile
+// Element work is done per tile of bricks: a workgroup per (tile, source), or
+// per tile with the sources in turn where a result is summed over sources (the
+// gradient); each thread keeps one node of the tile's node box.  The PML
+// operator runs as two launches, one per row type.  Scatter without atomics:
+// a node lies on the upper face (local index 2*count) of at most one tile per
+// axis, so the set c of axes on which it is an upper-face node differs for
+// every tile containing it.  A tile
 // stores its partial sum for a box node with a plain store into partial
 // array c; the nodal kernel adds the arrays c that can be non-zero for the
 // node.  Array 0 uses the register index spaces (full grid for u-rows, PML
@@ -30,10 +33,11 @@
 #pragma once
 #include "geometry.h"
 
-// Threads of an element-kernel workgroup (the kernels loop over the tile's
-// nodes and points in strides of the workgroup size).
+// Threads of an element-kernel workgroup: at least the tile's box nodes (one
+// node per thread; the kernels loop over the tile's LGL points in strides of
+// the workgroup size).  512 fits the 11 x 9 x 5 node box of a 5x4x2 tile.
 #ifndef PMLFWI_ETHREADS
-#define PMLFWI_ETHREADS 256
+#define PMLFWI_ETHREADS 512
 #endif
 
 namespace pmlfwi {

@@ -80,3 +80,23 @@ def test_checkpoint_spacing_shrinks_the_workspace():
     print({k: f"{v / 2**30:.1f} GiB" for k, v in sizes.items()}, f"k=0: {full / 2**30:.1f} GiB")
     assert all(v * 3 < full for v in sizes.values())
     assert sizes[50] < sizes[10] and sizes[50] < sizes[200]
+
+
+@pytest.mark.parametrize("name, make", [("tiny_ragged", lambda: W.tiny(ne_int=(3, 2, 3), npml_side=2, npml_bottom=1)),
+                                        ("cfg2", lambda: W.config2(nsteps=10))])
+def test_query_reports_a_tiling_that_covers_the_bricks(name, make):
+    """The element tiles reported by fwi_query partition the bricks: each tile
+    holds at most tile[0] x tile[1] x tile[2] bricks, interior and PML tiles
+    together cover every brick, and a workgroup holds the tile's node box."""
+    from paper_1504_08340_amd import binding
+    wl = make()
+    q = binding.fwi_query(binding.make_problem(wl.prob, 1, wl.nrec, 1, 0))
+    tx, ty, tz = q.tile
+    ex, ey, ez = wl.prob.ne_int
+    ps, pb = wl.prob.npml_side, wl.prob.npml_bottom
+    assert q.element_threads >= (2 * tx + 1) * (2 * ty + 1) * (2 * tz + 1)
+    assert q.tiles_interior == -(-ex // tx) * -(-ey // ty) * -(-ez // tz)
+    bricks = (ex + 2 * ps) * (ey + 2 * ps) * (ez + pb)
+    per_axis = [-(-ps // tx) * 2 + -(-ex // tx), -(-ps // ty) * 2 + -(-ey // ty), -(-pb // tz) + -(-ez // tz)]
+    assert q.tiles_interior + q.tiles_pml == per_axis[0] * per_axis[1] * per_axis[2]
+    assert (q.tiles_interior + q.tiles_pml) * tx * ty * tz >= bricks
