@@ -25,6 +25,10 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 
 enum { MFMA_F32 = 1, MFMA_BF16X3 = 3 };
 
+// Threads of a matrix-core workgroup (its waves take the 16x16 output tiles in
+// turn): 8 waves for FP32, 4 for the split BF16 form (145 VGPRs).
+constexpr int mfma_threads(int mode) { return mode == MFMA_BF16X3 ? 256 : 512; }
+
 // B[r][a]: derivative of local basis a along axis r / 27 at point r % 27.
 __device__ __forceinline__ float bref(int r, int a) {
   if (r >= 81 || a >= 27) return 0.0f;
@@ -91,9 +95,9 @@ __device__ __forceinline__ v4f mfma_tile(int row0, int col0, FA fa, FB fb) {
 }
 
 // r_u += K_RD u for the x1 displacement of the input register, bricks of the
-// tile list, one source per workgroup (blockIdx.y); 256 threads.
+// tile list, one source per workgroup (blockIdx.y); mfma_threads(MODE) threads.
 template <int MODE, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(mfma_threads(MODE))
 interior_mfma_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, const float* __restrict__ Ybase,
                      long long ystride, const float* __restrict__ lam, const float* __restrict__ mu,
                      float* __restrict__ rbase, Part PT) {
@@ -144,7 +148,7 @@ interior_mfma_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, const fl
     return ea < cx && eb < cy && ec < cz;
   };
   // G = B U
-  for (int tile = wave; tile < MT_G * NT; tile += 4) {
+  for (int tile = wave; tile < MT_G * NT; tile += mfma_threads(MODE) / 64) {
     const int mt = tile % MT_G, nt = tile / MT_G;
     auto fa = [&](int r, int a) { return bref(r, a); };
     auto fb = [&](int a, int c) -> float {
@@ -188,7 +192,7 @@ interior_mfma_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, const fl
   __syncthreads();
 
   // R = B^T S
-  for (int tile = wave; tile < MT_R * NT; tile += 4) {
+  for (int tile = wave; tile < MT_R * NT; tile += mfma_threads(MODE) / 64) {
     const int mt = tile % MT_R, nt = tile / MT_R;
     auto fa = [&](int a, int r) { return bref(r, a); };
     auto fb = [&](int r, int c) -> float { return (r < 81 && c < NC) ? sG[r][c] : 0.0f; };

@@ -625,10 +625,10 @@ struct Run {
       if (pr != FWI_FP32_MFMA && pr != FWI_FP32_BF16X3) return false;
       const dim3 grid(gx, p->nsrc);
       if (pr == FWI_FP32_MFMA)
-        interior_mfma_kernel<MFMA_F32, TX, TY, TZ><<<grid, 256, 0, st>>>(
+        interior_mfma_kernel<MFMA_F32, TX, TY, TZ><<<grid, mfma_threads(MFMA_F32), 0, st>>>(
             g(), p->d_tiles_int, nt, Y, (long long)L.reg_elems, lam(), mu(), res(), L.part);
       else
-        interior_mfma_kernel<MFMA_BF16X3, TX, TY, TZ><<<grid, 256, 0, st>>>(
+        interior_mfma_kernel<MFMA_BF16X3, TX, TY, TZ><<<grid, mfma_threads(MFMA_BF16X3), 0, st>>>(
             g(), p->d_tiles_int, nt, Y, (long long)L.reg_elems, lam(), mu(), res(), L.part);
       return true;
     }
