@@ -739,7 +739,10 @@ __device__ __forceinline__ R gather_rows(const Part& P, const PartSlots& S, cons
 // STORE writes the produced x1 displacement on the interior closure.
 // Threads [0, sn) take the displacement rows of node gid (none past n_nodes),
 // threads [sn, sn + n_pml) the PML rows; every load of a thread is issued
-// before its first store.
+// before its first store.  The accumulator is written and Xn read with
+// non-temporal hints: neither is touched again before the next stage's nodal
+// pass, so they should not displace the stage input and the residual partials
+// that the element kernels and this kernel share in the caches.
 template <typename R, int MODE, bool STORE>
 __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
@@ -770,7 +773,7 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
       u1[d] = Y[o1];
       u2[d] = Y[o2];
       rr[d] = gather_rows(A.part, PS, res, o1, d);
-      if (MODE != 2) { x1[d] = X[o1]; x2[d] = X[o2]; }
+      if (MODE != 2) { x1[d] = __builtin_nontemporal_load(&X[o1]); x2[d] = __builtin_nontemporal_load(&X[o2]); }
       if (MODE != 0) { c1[d] = C[o1]; c2[d] = C[o2]; }
     }
     const R im = A.invMu[node];
@@ -806,8 +809,8 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
         X[o1] = out1[d] = c1[d] + cA * u2[d];
         X[o2] = c2[d] + cA * a2[d];
       } else {
-        C[o1] = (MODE == 0 ? x1[d] : c1[d]) + cA * u2[d];
-        C[o2] = (MODE == 0 ? x2[d] : c2[d]) + cA * a2[d];
+        __builtin_nontemporal_store((MODE == 0 ? x1[d] : c1[d]) + cA * u2[d], &C[o1]);
+        __builtin_nontemporal_store((MODE == 0 ? x2[d] : c2[d]) + cA * a2[d], &C[o2]);
         Yo[o1] = out1[d] = x1[d] + cY * u2[d];
         Yo[o2] = x2[d] + cY * a2[d];
       }
@@ -859,7 +862,7 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   for (int q = 0; q < P_NCOMP; ++q) {
     const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
     const size_t o = (size_t)q * np + p;
-    if (live && MODE != 2) xv[q] = PX[o];
+    if (live && MODE != 2) xv[q] = __builtin_nontemporal_load(&PX[o]);
     if (live && MODE != 0) cv[q] = PC[o];
   }
 #pragma unroll
@@ -878,7 +881,7 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     if (MODE == 2) {
       PX[o] = cv[q] + cA * rate[q];
     } else {
-      PC[o] = (MODE == 0 ? xv[q] : cv[q]) + cA * rate[q];
+      __builtin_nontemporal_store((MODE == 0 ? xv[q] : cv[q]) + cA * rate[q], &PC[o]);
       PO[o] = xv[q] + cY * rate[q];
     }
   }
