@@ -352,6 +352,71 @@ def test_appendix_b_gradient_converges_to_discrete_gradient():
     assert gaps[0] / gaps[1] > 3.0, gaps
 
 
+# ---------------------------------------------------------------- time accuracy of (6) and the misfit (7)
+def _traces_at_dt(wl, dt, T, fc, stage_times="rk4"):
+    """Traces of a fixed model up to time T at step dt (load: Ricker of fc).
+
+    stage_times="rk4" is the oracle as it stands; "t_n" plants a mistake in
+    a copy of it (every stage sees the load at t_n) to show what the pin
+    catches."""
+    N = int(round(T / dt))
+    prob = wl.prob.replace(dt=dt, nsteps=N)
+    s = System(prob, wl.rho, wl.lam, wl.mu)
+    st = Stepper(s, wl.src_node, wl.src_dir, wl.rec_node)
+    if stage_times == "t_n":
+        exact = st.stages
+
+        def stages(X, wav, n):
+            w = wav.copy()
+            w[:, 2 * n + 1] = wav[:, 2 * n]
+            w[:, 2 * n + 2] = wav[:, 2 * n]
+            return exact(X, w, n)
+        st.stages = stages
+    wav = W.sample_wavelet(lambda t: W.ricker(t, fc), dt, N, 1000.0)[None]
+    tr, _ = st.forward(wav)
+    return tr
+
+
+@pytest.mark.parametrize("stage_times,lo,hi", [("rk4", 13.0, 19.0), ("t_n", 1.5, 2.5)])
+def test_forward_traces_converge_at_fourth_order_in_dt(stage_times, lo, hi):
+    """Classical RK4 with the load at t_n, t_n + dt/2 (twice), t_n + dt is
+    fourth-order accurate in time: on a PML mesh with a smooth load, the
+    trace differences between dt, dt/2 and dt/4 (same horizon T) fall by
+    2^4 = 16.  Sampling the load at t_n in every stage makes the scheme
+    first order in the forcing (ratio 2), which this pin rejects."""
+    wl = W.tiny(ne_int=(2, 2, 2), npml_side=1, npml_bottom=1, nsteps=1, seed=3)
+    dt, T, fc = 0.5 * wl.prob.dt, 0.08, 25.0
+    a, b, c = (_traces_at_dt(wl, dt / k, T, fc, stage_times) for k in (1, 2, 4))
+    d1 = np.linalg.norm(a - b[:, ::2])
+    d2 = np.linalg.norm(b[:, ::2] - c[:, ::4])
+    assert d2 > 0
+    assert lo < d1 / d2 < hi, (d1, d2)
+
+
+def test_misfit_trapezoid_closed_forms():
+    """(7) by the trapezoid rule over the step states: a constant residual r
+    in every component gives 1/2 r^2 T per component exactly; a residual
+    linear in time, a + b t, gives the trapezoid value of the quadratic
+    (a + b t)^2, which is its integral plus dt^2 (f'(T) - f'(0)) / 12
+    (Euler-Maclaurin ends at the first correction for a quadratic)."""
+    wl = W.tiny(ne_int=(2, 2, 2), npml_side=1, npml_bottom=1, nsteps=37, seed=3)
+    _, st = _stepper(wl)
+    N, dt = wl.prob.nsteps, wl.prob.dt
+    T = N * dt
+    nrec = len(wl.rec_node)
+    shape = (1, N + 1, nrec, 3)
+    r = 0.37
+    J = st.misfit(np.full(shape, r), np.zeros(shape))
+    np.testing.assert_allclose(J, 0.5 * r * r * T * nrec * 3, rtol=1e-13)
+    a, b = -0.8, 23.0
+    t = dt * np.arange(N + 1)
+    res = np.broadcast_to((a + b * t)[None, :, None, None], shape)
+    integral = ((a + b * T) ** 3 - a ** 3) / (3.0 * b)
+    trap = integral + dt * dt * (2.0 * b * b * T) / 12.0
+    J = st.misfit(np.array(res) + 1.5, np.full(shape, 1.5))
+    np.testing.assert_allclose(J, 0.5 * trap * nrec * 3, rtol=1e-12)
+
+
 # ---------------------------------------------------------------- time step of the paper
 def _material28_max():
     z = np.linspace(0.0, 45.0, 45001)
