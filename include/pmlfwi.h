@@ -40,11 +40,14 @@
  * Ownership: the caller allocates every array and the workspace (size from
  * fwi_query) and keeps them alive while work is enqueued.  A plan owns its
  * host metadata and a few KB of device metadata (brick tiles, source and
- * receiver tables) allocated by fwi_plan_create and released by
- * fwi_plan_destroy.  All work is enqueued on the given stream (a hipStream_t,
- * passed as void*; NULL is the default stream); no call synchronizes the host
- * with the device except fwi_plan_create (one upload) and argument checks
- * that read no device memory.
+ * receiver tables, misfit partial sums) and a second stream with two events,
+ * all created by fwi_plan_create and released by fwi_plan_destroy; the solves
+ * allocate nothing.  All work is enqueued on the given stream (a hipStream_t,
+ * passed as void*; NULL is the default stream).  The host waits for the
+ * device only in fwi_plan_create (one upload), fwi_check_model, the model
+ * check that fwi_forward, fwi_adjoint_gradient and fwi_adjoint_gradient_appb
+ * run before their first launch (one small kernel, a 40-byte copy and a
+ * synchronization of the stream), and fwi_timing_read.
  *
  * Errors: every call returns fwi_status; nothing throws across the ABI.  On
  * error no work has been enqueued (argument errors) or the HIP error is
@@ -66,7 +69,7 @@ typedef enum {
   FWI_ERR_SHAPE = -2,     /* mesh or time axis not representable */
   FWI_ERR_HIP = -3,       /* a HIP runtime call or kernel launch failed */
   FWI_ERR_STATE = -4,     /* call order violated (adjoint before forward) */
-  FWI_ERR_UNSTABLE = -5,  /* reserved: dt above the RK4 stability bound */
+  FWI_ERR_UNSTABLE = -5,  /* dt above the RK4 stability bound of the model */
   FWI_ERR_NOMEM = -6      /* host allocation failed */
 } fwi_status;
 
@@ -132,12 +135,19 @@ fwi_status fwi_plan_destroy(fwi_plan* plan);
 /* State problem (6): N RK4 steps from rest with the nodal load
  * src_dir[s] * wavelet[s][k] at the stage times; writes traces (u at every
  * receiver, steps 0..N) and keeps in the workspace what fwi_adjoint_gradient
- * needs (stage displacements or checkpoints). */
+ * needs (stage displacements or checkpoints).
+ * Before its first launch it checks the model as fwi_check_model does
+ * (synchronizing the stream): FWI_ERR_ARG when rho, mu or 3 lam + 2 mu is not
+ * positive somewhere, FWI_ERR_UNSTABLE when the plan's dt is above the RK4
+ * stability bound of this model; in both cases nothing else is enqueued and
+ * fwi_last_error names the offending values. */
 fwi_status fwi_forward(fwi_plan* plan, void* stream, const double* rho,
                        const double* lam, const double* mu,
                        const double* wavelet, void* workspace, double* traces);
 
-/* Misfit (7): residual = traces - observed and J (one double on the device). */
+/* Misfit (7): residual = traces - observed and J (one double on the device).
+ * J is summed per workgroup and then in a fixed order: the same inputs give
+ * the same bits. */
 fwi_status fwi_misfit(fwi_plan* plan, void* stream, const double* traces,
                       const double* observed, double* residual, double* J);
 
@@ -145,7 +155,11 @@ fwi_status fwi_misfit(fwi_plan* plan, void* stream, const double* traces,
  * fwi_forward on the same workspace and the same rho, lam, mu, wavelet.
  * Writes g_lam, g_mu (overwritten, summed over sources): the derivative of J
  * with respect to the nodal values on the closed interior, from the interior
- * bricks only (Sec. 3.1.3). */
+ * bricks only (Sec. 3.1.3).  PML nodes take their material from the closed
+ * interior box (the interface values carried outward), so on nodes of the
+ * interface the full derivative of J also has PML-brick terms that this
+ * restricted gradient leaves out; at every other node it is the exact
+ * derivative.  Checks the model as fwi_forward does. */
 fwi_status fwi_adjoint_gradient(fwi_plan* plan, void* stream, const double* rho,
                                 const double* lam, const double* mu,
                                 const double* wavelet, const double* residual,

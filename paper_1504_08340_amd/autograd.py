@@ -2,10 +2,16 @@
 
 ``misfit(lam, mu, solver, rho, wavelet, observed)`` returns J as a 0-d FP64
 tensor.  Its backward is the adjoint-state gradient of Sec. 3 (adjoint
-problem (15), gradient (18) with R = 0): the exact derivative of the discrete
-misfit with respect to the nodal lam and mu on the closed interior, the vector
-that finite differences of J converge to.  Both directions run in the HIP
-library behind ``solver``; this module only routes tensors.
+problem (15), gradient (18) with R = 0) restricted to the interior bricks as
+Sec. 3.1.3 prescribes: the derivative of the discrete misfit with respect to
+the nodal lam and mu on the closed interior, with the PML-brick terms left
+out.  PML nodes take their material from the interface nodes, so on nodes of
+the interface (the boundary of the closed interior box, free surface
+excepted) this vector is not the full derivative of J; everywhere else it is
+the exact derivative that finite differences of J converge to.  A caller who
+composes this function with other torch operations gets the restricted
+vector at the interface nodes.  Both directions run in the HIP library
+behind ``solver``; this module only routes tensors.
 
 The forward solve leaves in the solver's workspace what the adjoint sweep
 reads: every stage displacement (``ckpt_every = 0``) or a full state every k
@@ -28,6 +34,8 @@ class MisfitFunction(torch.autograd.Function):
         lam_c, mu_c = lam.detach().contiguous(), mu.detach().contiguous()
         traces = solver.forward(rho, lam_c, mu_c, wavelet)
         J, residual = solver.misfit(traces, observed)
+        if not torch.isfinite(J).all():
+            raise FloatingPointError(f"misfit is not finite ({J.item()}): the forward solve diverged")
         ctx.solver = solver
         ctx.generation = solver.generation
         ctx.save_for_backward(rho, lam_c, mu_c, wavelet, residual)

@@ -107,8 +107,15 @@ FWI_REG_TIKHONOV, FWI_REG_TV = 0, 1
 KERNEL_CLASSES = ("interior", "pml", "nodal", "interior_adj", "pml_adj")
 
 
+FWI_ERR_ARG, FWI_ERR_SHAPE, FWI_ERR_HIP, FWI_ERR_STATE, FWI_ERR_UNSTABLE, FWI_ERR_NOMEM = -1, -2, -3, -4, -5, -6
+
+
 class FwiError(RuntimeError):
-    pass
+    """A non-zero fwi_status; ``status`` holds the code."""
+
+    def __init__(self, msg, status=0):
+        super().__init__(msg)
+        self.status = status
 
 
 def _check(status, plan=None, what=""):
@@ -118,7 +125,7 @@ def _check(status, plan=None, what=""):
             detail = _lib.fwi_last_error(plan or None).decode()
             if detail:
                 msg += f": {detail}"
-        raise FwiError(f"{what} failed ({status}): {msg}")
+        raise FwiError(f"{what} failed ({status}): {msg}", status)
 
 
 def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0):

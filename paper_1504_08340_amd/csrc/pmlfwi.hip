@@ -53,6 +53,7 @@ struct fwi_plan {
   // mu = 0 and lam = 0, mu = 1 (stability bound of fwi_check_model)
   double c_lam = 0.0, c_mu = 0.0;
   double* d_info = nullptr;   // 5 doubles: device result of the model check
+  double* d_partials = nullptr;   // MISFIT_BLOCKS doubles: per-workgroup misfit sums
 };
 
 namespace {
@@ -419,9 +420,14 @@ __global__ void appb_force_kernel(R* __restrict__ Yout, R* __restrict__ Xn, R* _
   }
 }
 
-__global__ void misfit_kernel(const double* __restrict__ tr, const double* __restrict__ obs,
-                              double* __restrict__ resid, long long n, int per_step, int nsteps,
-                              double half_dt, double* __restrict__ J) {
+// Misfit (7): residual and per-workgroup sums of w_n r^2 (trapezoid weights),
+// then one workgroup adds the partial sums in a fixed order, so J has the same
+// bits on every run (the grid size depends only on the trace length).
+constexpr int MISFIT_BLOCKS = 2048;
+
+__global__ void __launch_bounds__(256) misfit_kernel(const double* __restrict__ tr, const double* __restrict__ obs,
+                                                     double* __restrict__ resid, long long n, int per_step,
+                                                     int nsteps, double* __restrict__ partials) {
   __shared__ double part[256];
   double acc = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
@@ -437,7 +443,21 @@ __global__ void misfit_kernel(const double* __restrict__ tr, const double* __res
     if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(J, half_dt * part[0]);
+  if (threadIdx.x == 0) partials[blockIdx.x] = part[0];
+}
+
+__global__ void __launch_bounds__(256) misfit_final_kernel(const double* __restrict__ partials, int nb,
+                                                           double half_dt, double* __restrict__ J) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partials[b];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J[0] = half_dt * part[0];
 }
 
 // x1 displacement of a register on the interior closure -> stage store slot.
@@ -656,11 +676,6 @@ struct Run {
     const bool pml = !interior_only && !p->tiles_pml.empty();
     const bool fork = PMLFWI_CONCURRENT && !p->tiles_int.empty() && pml;
     if (fork) {
-      if (!p->side) {
-        HIP_TRY(p, hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-        HIP_TRY(p, hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
-        HIP_TRY(p, hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
-      }
       HIP_TRY(p, hipEventRecord(p->fork_ev, st));
       HIP_TRY(p, hipStreamWaitEvent(p->side, p->fork_ev, 0));
       si = p->side;
@@ -918,6 +933,37 @@ struct Run {
   }
 };
 
+// Model check before a solve: one small kernel, a copy of 5 doubles and a
+// stream synchronization.  info: 6 host doubles (see fwi_check_model).
+fwi_status check_model(fwi_plan* p, hipStream_t st, const double* rho, const double* lam, const double* mu,
+                       double* info, const char* who) {
+  model_check_kernel<<<1, 1024, 0, st>>>(p->g, rho, lam, mu, p->c_lam, p->c_mu, p->d_info);
+  hipError_t e = hipGetLastError();
+  double v[5] = {0, 0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(v, p->d_info, sizeof(v), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(p, FWI_ERR_HIP, std::string(who) + ": model check: " + hipGetErrorString(e));
+  // omega_max^2 <= max over bricks of the brick bound; the unit reference brick
+  // has edge 2, so a brick of edge h scales it by (2/h)^2
+  const double h = p->g.h;
+  const double wmax = std::sqrt(v[4] * 4.0 / (h * h));
+  for (int k = 0; k < 4; ++k) info[k] = v[k];
+  info[4] = wmax;
+  info[5] = wmax > 0 ? 2.0 * std::sqrt(2.0) / wmax : HUGE_VAL;
+  char msg[256];
+  if (!(v[0] > 0.0) || !(v[1] > 0.0) || !(v[2] > 0.0)) {
+    std::snprintf(msg, sizeof(msg), "%s: rho, mu and 3 lam + 2 mu must be positive (min rho %g, min mu %g, "
+                  "min 3 lam + 2 mu %g)", who, v[0], v[1], v[2]);
+    return fail(p, FWI_ERR_ARG, msg);
+  }
+  if (!(p->prob.dt <= info[5])) {
+    std::snprintf(msg, sizeof(msg), "%s: dt %.6g s above the RK4 stability bound %.6g s (omega_max %.6g 1/s)",
+                  who, p->prob.dt, info[5], wmax);
+    return fail(p, FWI_ERR_UNSTABLE, msg);
+  }
+  return FWI_OK;
+}
+
 template <typename F>
 fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f) {
   Layout L = layout(p->prob, p->g);
@@ -1010,6 +1056,18 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   step("face ordinals", (void**)&p->d_fo, p->fo.data(), p->fo.size() * sizeof(int));
   const double zeros[5] = {0, 0, 0, 0, 0};
   step("model-check buffer", (void**)&p->d_info, zeros, sizeof(zeros));
+  if (e == hipSuccess) {
+    what = "misfit partial sums";
+    e = hipMalloc((void**)&p->d_partials, MISFIT_BLOCKS * sizeof(double));
+  }
+  // the stream the interior bricks run on beside the PML bricks, and its
+  // fork / join events (created here so that the solves allocate nothing)
+  if (e == hipSuccess) {
+    what = "side stream";
+    e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
   p->g.tab = p->d_tab;
   p->g.fo = p->d_fo;
   if (e != hipSuccess) {
@@ -1066,6 +1124,7 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
   (void)hipFree(p->d_tab);
   (void)hipFree(p->d_fo);
   (void)hipFree(p->d_info);
+  (void)hipFree(p->d_partials);
   delete p;
   return FWI_OK;
 }
@@ -1076,6 +1135,8 @@ fwi_status fwi_forward(fwi_plan* p, void* stream, const double* rho, const doubl
   if (!rho || !lam || !mu || !wavelet || !workspace || (p->nrec > 0 && !traces))
     return fail(p, FWI_ERR_ARG, "fwi_forward: null pointer");
   p->fwd_ws = nullptr;
+  double info[6];
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_forward"); c != FWI_OK) return c;
   fwi_status s = dispatch(p, (hipStream_t)stream, workspace,
                           [&](auto& r) { return r.forward(rho, lam, mu, wavelet, traces); });
   if (s == FWI_OK) p->fwd_ws = workspace;
@@ -1087,12 +1148,13 @@ fwi_status fwi_misfit(fwi_plan* p, void* stream, const double* traces, const dou
   if (!p) return FWI_ERR_ARG;
   if (!traces || !observed || !residual || !J) return fail(p, FWI_ERR_ARG, "fwi_misfit: null pointer");
   hipStream_t st = (hipStream_t)stream;
-  fill_kernel<double><<<1, 32, 0, st>>>(J, 1, 0.0);
   const long long n = (long long)p->nsrc * (p->prob.nsteps + 1) * p->nrec * 3;
-  if (n > 0) {
-    const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 2048);
-    misfit_kernel<<<nb, 256, 0, st>>>(traces, observed, residual, n, p->nrec * 3, p->prob.nsteps,
-                                      0.5 * p->prob.dt, J);
+  if (n == 0) {
+    fill_kernel<double><<<1, 32, 0, st>>>(J, 1, 0.0);
+  } else {
+    const int nb = (int)std::min<long long>((n + 255) / 256, MISFIT_BLOCKS);
+    misfit_kernel<<<nb, 256, 0, st>>>(traces, observed, residual, n, p->nrec * 3, p->prob.nsteps, p->d_partials);
+    misfit_final_kernel<<<1, 256, 0, st>>>(p->d_partials, nb, 0.5 * p->prob.dt, J);
   }
   HIP_TRY(p, hipGetLastError());
   return FWI_OK;
@@ -1106,6 +1168,8 @@ fwi_status fwi_adjoint_gradient(fwi_plan* p, void* stream, const double* rho, co
     return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient: null pointer");
   if (p->fwd_ws != workspace)
     return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient: no fwi_forward on this workspace");
+  double info[6];
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_adjoint_gradient"); c != FWI_OK) return c;
   return dispatch(p, (hipStream_t)stream, workspace,
                   [&](auto& r) { return r.adjoint(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
 }
@@ -1118,6 +1182,8 @@ fwi_status fwi_adjoint_gradient_appb(fwi_plan* p, void* stream, const double* rh
     return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient_appb: null pointer");
   if (p->fwd_ws != workspace)
     return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient_appb: no fwi_forward on this workspace");
+  double info[6];
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_adjoint_gradient_appb"); c != FWI_OK) return c;
   return dispatch(p, (hipStream_t)stream, workspace,
                   [&](auto& r) { return r.adjoint_appb(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
 }
@@ -1171,26 +1237,7 @@ fwi_status fwi_check_model(fwi_plan* p, void* stream, const double* rho, const d
                            double* info) {
   if (!p) return FWI_ERR_ARG;
   if (!rho || !lam || !mu || !info) return fail(p, FWI_ERR_ARG, "fwi_check_model: null pointer");
-  hipStream_t st = (hipStream_t)stream;
-  double* d = nullptr;
-  d = p->d_info;
-  model_check_kernel<<<1, 1024, 0, st>>>(p->g, rho, lam, mu, p->c_lam, p->c_mu, d);
-  hipError_t e = hipGetLastError();
-  double v[5] = {0, 0, 0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(v, d, sizeof(v), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  HIP_TRY(p, e);
-  // omega_max^2 <= max over bricks of the brick bound; the unit reference brick
-  // has edge 2, so a brick of edge h scales it by (2/h)^2
-  const double h = p->g.h;
-  const double wmax = std::sqrt(v[4] * 4.0 / (h * h));
-  for (int k = 0; k < 4; ++k) info[k] = v[k];
-  info[4] = wmax;
-  info[5] = wmax > 0 ? 2.0 * std::sqrt(2.0) / wmax : HUGE_VAL;
-  if (!(v[0] > 0.0) || !(v[1] > 0.0) || !(v[2] > 0.0))
-    return fail(p, FWI_ERR_ARG, "fwi_check_model: rho, mu and 3 lam + 2 mu must be positive");
-  if (p->prob.dt > info[5]) return fail(p, FWI_ERR_UNSTABLE, "fwi_check_model: dt above the RK4 stability bound");
-  return FWI_OK;
+  return check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_check_model");
 }
 
 fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b, const double* w, double* out) {

@@ -24,6 +24,8 @@ Choices the paper leaves open:
 """
 from __future__ import annotations
 
+import math
+
 import time
 from dataclasses import dataclass, field
 
@@ -83,16 +85,21 @@ class FwiStage:
         which the line search then rejects."""
         lam, mu = lam.contiguous(), mu.contiguous()
         try:
-            B.fwi_check_model(self.S.plan, None, self.rho, lam, mu)
-        except B.FwiError:
+            tr = self.S.forward(self.rho, lam, mu, self.wav)   # checks the model first
+        except B.FwiError as e:
+            if e.status not in (B.FWI_ERR_ARG, B.FWI_ERR_UNSTABLE):
+                raise
             self.last_J = float("inf")
             self._lam = None
             return self.last_J
-        tr = self.S.forward(self.rho, lam, mu, self.wav)
         _, self._res = self.S.misfit(tr, self.obs, J=self._J)
         self._lam, self._mu = lam, mu
         self.counts[0] += 1
         self.last_J = float(self._J[0])
+        if not math.isfinite(self.last_J):
+            # a stable dt cannot blow up; treat it like a rejected model
+            self.last_J = float("inf")
+            self._lam = None
         return self.last_J
 
     def gradient(self):

@@ -11,6 +11,23 @@ import torch
 from . import binding as B
 
 
+def check_tensor(name, t, numel, device, dtype=torch.float64):
+    """Raise ValueError unless t is a contiguous tensor of dtype on device with
+    numel elements: the C entry points take raw pointers and would read or
+    write past a short or mistyped buffer."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    return t
+
+
 class Solver:
     """One plan + workspace on a CUDA/HIP device.
 
@@ -24,6 +41,8 @@ class Solver:
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (HIP device); no CPU fallback exists")
         self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.nsrc = int(len(src_node))
         self.nrec = int(len(rec_node))
         self.problem = B.make_problem(prob, self.nsrc, self.nrec, precision, ckpt_every)
@@ -56,9 +75,27 @@ class Solver:
     def empty_traces(self):
         return torch.empty(self.trace_shape, dtype=torch.float64, device=self.device)
 
+    # -- argument checks (before any C call) ---------------------------------
+    def _model(self, rho, lam, mu):
+        n = int(self.sizes.n_int_nodes)
+        for name, t in (("rho", rho), ("lam", lam), ("mu", mu)):
+            check_tensor(name, t, n, self.device)
+
+    def _wavelet(self, wavelet):
+        check_tensor("wavelet", wavelet, self.nsrc * (2 * self.nsteps + 1), self.device)
+
+    def _trace(self, name, t):
+        check_tensor(name, t, int(np.prod(self.trace_shape)), self.device)
+
+    def _nodal(self, name, t):
+        check_tensor(name, t, self.nsrc * 9 * int(self.sizes.n_nodes), self.device)
+
     # -- C ABI calls -------------------------------------------------------
     def forward(self, rho, lam, mu, wavelet, traces=None, stream=None):
         traces = self.empty_traces() if traces is None else traces
+        self._model(rho, lam, mu)
+        self._wavelet(wavelet)
+        self._trace("traces", traces)
         self.generation += 1
         B.fwi_forward(self.plan, stream, rho, lam, mu, wavelet, self.workspace, traces)
         return traces
@@ -66,6 +103,9 @@ class Solver:
     def misfit(self, traces, observed, residual=None, J=None, stream=None):
         residual = torch.empty_like(traces) if residual is None else residual
         J = torch.empty(1, dtype=torch.float64, device=self.device) if J is None else J
+        for name, t in (("traces", traces), ("observed", observed), ("residual", residual)):
+            self._trace(name, t)
+        check_tensor("J", J, 1, self.device)
         B.fwi_misfit(self.plan, stream, traces, observed, residual, J)
         return J, residual
 
@@ -76,11 +116,19 @@ class Solver:
         n = int(self.sizes.n_int_nodes)
         g_lam = torch.empty(n, dtype=torch.float64, device=self.device) if g_lam is None else g_lam
         g_mu = torch.empty(n, dtype=torch.float64, device=self.device) if g_mu is None else g_mu
+        self._model(rho, lam, mu)
+        self._wavelet(wavelet)
+        self._trace("residual", residual)
+        check_tensor("g_lam", g_lam, n, self.device)
+        check_tensor("g_mu", g_mu, n, self.device)
         fn = {"discrete": B.fwi_adjoint_gradient, "appb": B.fwi_adjoint_gradient_appb}[scheme]
         fn(self.plan, stream, rho, lam, mu, wavelet, residual, self.workspace, g_lam, g_mu)
         return g_lam, g_mu
 
     def apply_operator(self, which, rho, lam, mu, x0, x1, x2, out=None, stream=None):
         out = torch.empty_like(x1) if out is None else out
+        self._model(rho, lam, mu)
+        for name, t in (("x0", x0), ("x1", x1), ("x2", x2), ("out", out)):
+            self._nodal(name, t)
         B.fwi_apply_operator(self.plan, stream, which, rho, lam, mu, x0, x1, x2, self.workspace, out)
         return out

@@ -70,3 +70,82 @@ def test_workloads_pass_the_check(P, make):
     print(f"{wl.name}: dt {wl.prob.dt:.3e} <= stable {info[5]:.3e}")
     assert wl.prob.dt <= info[5]
     S.close()
+
+
+def test_forward_and_adjoint_validate_the_model_before_any_launch(P):
+    """fwi_forward / fwi_adjoint_gradient run the model check first: a step past
+    the bound returns FWI_ERR_UNSTABLE, a negative mu or bulk term
+    FWI_ERR_ARG, and nothing else is enqueued (the trace buffer keeps its
+    sentinel values)."""
+    import torch
+    wl = W.tiny(ne_int=(2, 2, 2), npml_side=1, npml_bottom=1, nsteps=5, seed=3)
+    S = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    rho, lam, mu, wav = (S.tensor(a) for a in (wl.rho, wl.lam, wl.mu, wl.wavelet))
+    info = P.fwi_check_model(S.plan, None, rho, lam, mu)
+    S.close()
+    fast = wl.prob.replace(dt=1.5 * info[5])
+    S2 = P.Solver(fast, wl.src_node, wl.src_dir, wl.rec_node)
+    tr = torch.full(S2.trace_shape, 7.0, dtype=torch.float64, device=S2.device)
+    with pytest.raises(P.FwiError, match="stability") as e:
+        S2.forward(rho, lam, mu, wav, tr)
+    assert e.value.status == -5
+    torch.cuda.synchronize()
+    assert bool((tr == 7.0).all())
+    S2.close()
+    S3 = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    for field, bad in (("mu", -1.0), ("lam", -1e12)):
+        m = {"lam": wl.lam.copy(), "mu": wl.mu.copy()}
+        m[field][5] = bad
+        tr = torch.full(S3.trace_shape, 7.0, dtype=torch.float64, device=S3.device)
+        with pytest.raises(P.FwiError, match="positive") as e:
+            S3.forward(rho, S3.tensor(m["lam"]), S3.tensor(m["mu"]), wav, tr)
+        assert e.value.status == -1
+        torch.cuda.synchronize()
+        assert bool((tr == 7.0).all())
+    # a good forward, then an adjoint with a non-physical model: rejected too
+    tr = S3.forward(rho, lam, mu, wav)
+    J, res = S3.misfit(tr, torch.zeros_like(tr))
+    bad = wl.mu.copy()
+    bad[3] = 0.0
+    with pytest.raises(P.FwiError, match="positive"):
+        S3.adjoint_gradient(rho, lam, S3.tensor(bad), wav, res)
+    S3.close()
+
+
+def test_solver_rejects_mistyped_and_short_buffers(P):
+    """Argument checks in Solver run before any C call."""
+    import torch
+    wl = W.tiny(ne_int=(2, 2, 2), npml_side=1, npml_bottom=1, nsteps=5, seed=3)
+    S = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    rho, lam, mu, wav = (S.tensor(a) for a in (wl.rho, wl.lam, wl.mu, wl.wavelet))
+    with pytest.raises(ValueError, match="dtype"):
+        S.forward(rho, lam.float(), mu, wav)
+    with pytest.raises(ValueError, match="expected cuda"):
+        S.forward(rho, lam, mu.cpu(), wav)
+    with pytest.raises(ValueError, match="elements"):
+        S.forward(rho, lam, mu, wav[:, :-3].contiguous())
+    with pytest.raises(ValueError, match="contiguous"):
+        S.forward(rho, lam, mu, torch.cat([wav, wav], 1)[:, ::2])
+    tr = S.forward(rho, lam, mu, wav)
+    with pytest.raises(ValueError, match="elements"):
+        S.misfit(tr, torch.zeros(tr.numel() - 1, dtype=torch.float64, device=S.device))
+    J, res = S.misfit(tr, torch.zeros_like(tr))
+    with pytest.raises(ValueError, match="g_lam"):
+        S.adjoint_gradient(rho, lam, mu, wav, res, g_lam=torch.empty(3, dtype=torch.float64, device=S.device))
+    S.close()
+
+
+def test_misfit_is_bit_reproducible(P):
+    import torch
+    wl = W.config1(nsteps=60)
+    S = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    rho, lam, mu, wav = (S.tensor(a) for a in (wl.rho, wl.lam, wl.mu, wl.wavelet))
+    tr = S.forward(rho, lam, mu, wav)
+    obs = 0.5 * tr
+    Js = []
+    for _ in range(3):
+        J, _ = S.misfit(tr, obs)
+        Js.append(J.item())
+    torch.cuda.synchronize()
+    assert Js[0] == Js[1] == Js[2]
+    S.close()
