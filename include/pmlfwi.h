@@ -145,6 +145,25 @@ fwi_status fwi_forward(fwi_plan* plan, void* stream, const double* rho,
                        const double* lam, const double* mu,
                        const double* wavelet, void* workspace, double* traces);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the state
+ * problem of fwi_forward (same kernels, same traces) with no workspace
+ * argument.  Its workspace is a fixed device array of the library, 64 MiB
+ * per GPU (allocated when the library is loaded, held until the process
+ * ends); its device address is looked up by fwi_plan_create, and the plan
+ * must be used on the device that was current then (else FWI_ERR_ARG).
+ * It keeps nothing for an adjoint (no stage store, no checkpoints) and leaves
+ * the plan's record of the last fwi_forward untouched.  Problems whose
+ * forward registers, residual arrays and materials exceed 64 MiB are rejected
+ * with FWI_ERR_ARG before any launch.  Every call on one GPU uses the same
+ * array: calls that overlap in time on one GPU (several streams, threads or
+ * plans) race and give wrong traces; serialize them.  Model check, stream
+ * synchronization and errors as fwi_forward; the call allocates nothing
+ * (kernel timing is suspended during the call). */
+fwi_status fwi_forward_noalloc(fwi_plan* plan, void* stream, const double* rho,
+                               const double* lam, const double* mu,
+                               const double* wavelet, double* traces);
+
 /* Misfit (7): residual = traces - observed and J (one double on the device).
  * J is summed per workgroup and then in a fixed order: the same inputs give
  * the same bits. */

@@ -60,6 +60,7 @@ _lib.fwi_query.argtypes = [ctypes.POINTER(fwi_problem), ctypes.POINTER(fwi_sizes
 _lib.fwi_plan_create.argtypes = [ctypes.POINTER(fwi_problem), _P, _P, _P, ctypes.POINTER(_P)]
 _lib.fwi_plan_destroy.argtypes = [_P]
 _lib.fwi_forward.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
+_lib.fwi_forward_noalloc.argtypes = [_P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_misfit.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.fwi_adjoint_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_adjoint_gradient_appb.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -91,14 +92,14 @@ _lib.fwi_adam.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _F, _F, _F, _F, ct
 _lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _P]
 _lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]
-for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
+for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_misfit",
+EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
@@ -184,6 +185,11 @@ def _stream(stream):
 def fwi_forward(plan, stream, rho, lam, mu, wavelet, workspace, traces):
     _check(_lib.fwi_forward(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu), _ptr(wavelet),
                             _ptr(workspace), _ptr(traces)), plan, "fwi_forward")
+
+
+def fwi_forward_noalloc(plan, stream, rho, lam, mu, wavelet, traces):
+    _check(_lib.fwi_forward_noalloc(plan, _stream(stream), _ptr(rho), _ptr(lam), _ptr(mu), _ptr(wavelet),
+                                    _ptr(traces)), plan, "fwi_forward_noalloc")
 
 
 def fwi_misfit(plan, stream, traces, observed, residual, J):

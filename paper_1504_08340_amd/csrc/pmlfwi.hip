@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -54,6 +55,9 @@ struct fwi_plan {
   double c_lam = 0.0, c_mu = 0.0;
   double* d_info = nullptr;   // 5 doubles: device result of the model check
   double* d_partials = nullptr;   // MISFIT_BLOCKS doubles: per-workgroup misfit sums
+  double* h_info = nullptr;       // 5 doubles of pinned host memory: the model check's result
+  int device = 0;                 // device current at fwi_plan_create
+  void* scratch = nullptr;        // device address of the fixed scratch array on that device
 };
 
 namespace {
@@ -311,7 +315,9 @@ int count_faces(const fwi_problem& P, const Geo& g, int d) {
   return (int)axis_segments(g.pb, g.ez, 0, TZ).size();
 }
 
-Layout layout(const fwi_problem& P, const Geo& g) {
+// keep = false: a forward solve that keeps nothing for the adjoint (no stage
+// store, no checkpoints, no gradient accumulators).
+Layout layout(const fwi_problem& P, const Geo& g, bool keep = true) {
   Layout L{};
   const int nface[3] = {count_faces(P, g, 0), count_faces(P, g, 1), count_faces(P, g, 2)};
   L.part = part_layout(g, nface, 9, true);
@@ -321,16 +327,16 @@ Layout layout(const fwi_problem& P, const Geo& g) {
   L.res_elems = 3 * (size_t)g.sn + 6 * (size_t)g.sp;
   L.stage_elems = (size_t)P.nsrc * 3 * g.si;
   const int k = P.ckpt_every;
-  L.nreg = k == 0 ? 4 : 8;
-  L.nstore = k == 0 ? P.nsteps : std::min(k, P.nsteps);
-  L.nckpt = k == 0 ? 0 : (P.nsteps + k - 1) / k;
+  L.nreg = (k == 0 || !keep) ? 4 : 8;
+  L.nstore = !keep ? 0 : (k == 0 ? P.nsteps : std::min(k, P.nsteps));
+  L.nckpt = (k == 0 || !keep) ? 0 : (P.nsteps + k - 1) / k;
   size_t o = 0;
   L.off_lam = o; o = align256(o + (size_t)g.n_int * L.es);
   L.off_mu = o; o = align256(o + (size_t)g.n_int * L.es);
   L.off_invm = o; o = align256(o + (size_t)g.n_nodes * L.es);
   L.off_regs = o; o = align256(o + (size_t)L.nreg * P.nsrc * L.reg_elems * L.es);
   L.off_res = o; o = align256(o + (size_t)P.nsrc * L.part.per_src * L.es);
-  L.off_gacc = o; o = align256(o + (size_t)L.gpart.per_src * sizeof(double));
+  L.off_gacc = o; o = align256(o + (keep ? (size_t)L.gpart.per_src * sizeof(double) : 0));
   L.off_store = o; o = align256(o + (size_t)L.nstore * 4 * L.stage_elems * L.es);
   L.off_ckpt = o; o = align256(o + (size_t)L.nckpt * P.nsrc * L.reg_elems * L.es);
   L.total = o;
@@ -791,18 +797,20 @@ struct Run {
     return FWI_OK;
   }
 
+  // keep = false: traces only, nothing kept for the adjoint.
   fwi_status forward(const double* rho, const double* lam_, const double* mu_, const double* wav,
-                     double* traces) {
+                     double* traces, bool keep = true) {
     const fwi_problem& P = p->prob;
     fwi_status e;
     if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
     if ((e = zero_regs(0, 4)) != FWI_OK) return e;
     const size_t tl = (size_t)P.nsrc * (P.nsteps + 1) * p->nrec * 3;
     if ((e = fill<double>(traces, tl, 0.0)) != FWI_OK) return e;
-    const bool keep_all = P.ckpt_every == 0;
+    const bool keep_all = keep && P.ckpt_every == 0;
+    const bool ckpts = keep && P.ckpt_every > 0;
     if (keep_all && (e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
     for (int n = 0; n < P.nsteps; ++n) {
-      if (!keep_all && n % P.ckpt_every == 0)
+      if (ckpts && n % P.ckpt_every == 0)
         HIP_TRY(p, hipMemcpyAsync(ckpt(n / P.ckpt_every), reg(0), (size_t)P.nsrc * L.reg_elems * L.es,
                                   hipMemcpyDeviceToDevice, st));
       if ((e = step(false, 0, n, wav, keep_all ? n : -1, n + 1 < P.nsteps, -1)) != FWI_OK)
@@ -939,10 +947,10 @@ fwi_status check_model(fwi_plan* p, hipStream_t st, const double* rho, const dou
                        double* info, const char* who) {
   model_check_kernel<<<1, 1024, 0, st>>>(p->g, rho, lam, mu, p->c_lam, p->c_mu, p->d_info);
   hipError_t e = hipGetLastError();
-  double v[5] = {0, 0, 0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(v, p->d_info, sizeof(v), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->h_info, p->d_info, 5 * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(p, FWI_ERR_HIP, std::string(who) + ": model check: " + hipGetErrorString(e));
+  const double* v = p->h_info;
   // omega_max^2 <= max over bricks of the brick bound; the unit reference brick
   // has edge 2, so a brick of edge h scales it by (2/h)^2
   const double h = p->g.h;
@@ -965,8 +973,8 @@ fwi_status check_model(fwi_plan* p, hipStream_t st, const double* rho, const dou
 }
 
 template <typename F>
-fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f) {
-  Layout L = layout(p->prob, p->g);
+fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f, bool keep = true) {
+  Layout L = layout(p->prob, p->g, keep);
   if (p->prob.precision != FWI_FP64) {
     Run<float> r{p, st, L, (char*)ws};
     return f(r);
@@ -975,6 +983,37 @@ fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f) {
   return f(r);
 }
 
+}  // namespace
+
+// ------------------------------------------------ fixed scratch (no allocation)
+// Workspace of fwi_forward_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name as
+// an address: the device address is looked up once per device
+// (hipGetSymbolAddress, at fwi_plan_create with that device current) and
+// kept in g_scratch_addr and in every plan made on that device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of the scratch array on `device` (which must be current).
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1068,6 +1107,18 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    what = "pinned model-check result";
+    e = hipHostMalloc((void**)&p->h_info, 5 * sizeof(double), hipHostMallocDefault);
+  }
+  if (e == hipSuccess) {
+    what = "device id";
+    e = hipGetDevice(&p->device);
+  }
+  if (e == hipSuccess) {
+    what = "address of the fixed scratch array";
+    e = scratch_address(p->device, &p->scratch);
+  }
   p->g.tab = p->d_tab;
   p->g.fo = p->d_fo;
   if (e != hipSuccess) {
@@ -1125,6 +1176,7 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
   (void)hipFree(p->d_fo);
   (void)hipFree(p->d_info);
   (void)hipFree(p->d_partials);
+  if (p->h_info) (void)hipHostFree(p->h_info);
   delete p;
   return FWI_OK;
 }
@@ -1140,6 +1192,35 @@ fwi_status fwi_forward(fwi_plan* p, void* stream, const double* rho, const doubl
   fwi_status s = dispatch(p, (hipStream_t)stream, workspace,
                           [&](auto& r) { return r.forward(rho, lam, mu, wavelet, traces); });
   if (s == FWI_OK) p->fwd_ws = workspace;
+  return s;
+}
+
+fwi_status fwi_forward_noalloc(fwi_plan* p, void* stream, const double* rho, const double* lam, const double* mu,
+                               const double* wavelet, double* traces) {
+  if (!p) return FWI_ERR_ARG;
+  if (!rho || !lam || !mu || !wavelet || (p->nrec > 0 && !traces))
+    return fail(p, FWI_ERR_ARG, "fwi_forward_noalloc: null pointer");
+  if (!p->scratch) return fail(p, FWI_ERR_HIP, "fwi_forward_noalloc: no scratch address for this device");
+  int dev = -1;
+  HIP_TRY(p, hipGetDevice(&dev));
+  if (dev != p->device) return fail(p, FWI_ERR_ARG, "fwi_forward_noalloc: the plan belongs to another device");
+  const size_t need = layout(p->prob, p->g, false).total;
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg), "fwi_forward_noalloc: this problem needs %zu bytes of workspace, more than "
+                  "the fixed scratch of %zu bytes", need, NOALLOC_SCRATCH_BYTES);
+    return fail(p, FWI_ERR_ARG, msg);
+  }
+  double info[6];
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_forward_noalloc"); c != FWI_OK)
+    return c;
+  // the forward registers in the plan's workspace (if any) are not touched, so
+  // an fwi_adjoint_gradient after this call still sees the last fwi_forward
+  const int tstride = p->tstride;   // sampled timing would create events
+  p->tstride = 0;
+  fwi_status s = dispatch(p, (hipStream_t)stream, p->scratch,
+                          [&](auto& r) { return r.forward(rho, lam, mu, wavelet, traces, false); }, false);
+  p->tstride = tstride;
   return s;
 }
 
