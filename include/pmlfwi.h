@@ -101,7 +101,8 @@ typedef struct {
                              every RK4 stage, the adjoint recomputes nothing;
                              k > 0: the forward keeps the full state every k
                              steps and the adjoint recomputes one k-step segment
-                             at a time */
+                             at a time; -1: forward-only plan (traces only,
+                             no adjoint; smallest workspace) */
 } fwi_problem;
 
 typedef struct {
@@ -131,6 +132,27 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node,
                            const double* src_dir, const int32_t* rec_node,
                            fwi_plan** out);
 fwi_status fwi_plan_destroy(fwi_plan* plan);
+
+/* Replace the point loads of fwi_plan_create by a general list of nodal
+ * loads (Sec. 4: vertical stress loads over a surface region): entry e adds
+ * load_vec[e][0..2] * wavelet[load_src[e]][k] [N] at full-grid node
+ * load_node[e] (not a Dirichlet node) in the stage of time k*dt/2.  Host
+ * arrays, copied; entries with the same (source, node) are summed.  nload = 0
+ * returns to the point loads.  A set-up call: it waits for the device and
+ * allocates the plan's load tables. */
+fwi_status fwi_plan_set_loads(fwi_plan* plan, int32_t nload, const int32_t* load_src,
+                              const int32_t* load_node, const double* load_vec);
+
+/* Consistent nodal weights of a uniform traction on the free surface z = 0
+ * over the rectangle [xmin, xmax] x [ymin, ymax] (whole brick faces inside
+ * it): weight[c] = integral over the region of the basis function of node[c],
+ * by the 3x3 LGL rule of each face, i.e. products of the 1D weights
+ * (h/6, 2h/3, h/6) summed over the faces containing the node.  A traction t
+ * [Pa] in direction d gives the load t * weight[c] * d.  Host function; the
+ * first min(count, cap) entries are written; FWI_ERR_SHAPE when count > cap. */
+fwi_status fwi_surface_traction(const fwi_problem* prob, double xmin, double xmax,
+                                double ymin, double ymax, int32_t cap, int32_t* node,
+                                double* weight, int32_t* count);
 
 /* State problem (6): N RK4 steps from rest with the nodal load
  * src_dir[s] * wavelet[s][k] at the stage times; writes traces (u at every

@@ -48,13 +48,20 @@ class Stepper:
     ``residual_T3``, ``Minv``, ``hist``, ``mesh``, ``g`` (the assembled
     ``System`` or the element-batched ``MatFree``)."""
 
-    def __init__(self, system, src_node, src_dir, rec_node):
+    def __init__(self, system, src_node, src_dir, rec_node, loads=None):
+        """loads: optional (load_src, load_node, load_vec) list of nodal loads
+        (distributed surface tractions, ``oracle.loads``) replacing the point
+        loads src_node / src_dir; the number of sources stays len(src_node)."""
         s = system
         self.s = s
         self.dt = s.prob.dt
         self.N = s.prob.nsteps
         self.nh, self.ns = s.n_hist, s.n_state
-        self.Fsrc = source_vectors(s.mesh, s.n_state, src_node, src_dir)   # (n_state, nsrc)
+        if loads is None:
+            self.Fsrc = source_vectors(s.mesh, s.n_state, src_node, src_dir)   # (n_state, nsrc)
+        else:
+            from .loads import load_matrix
+            self.Fsrc = load_matrix(s.mesh, s.mesh.u_dof, s.n_state, len(src_node), *loads)
         self.rec = receiver_dofs(s.mesh, rec_node)                          # (nrec, 3)
 
     # -- X is (n_X, nsrc): [x0 (n_hist); x1 (n_state); x2 (n_state)]

@@ -61,6 +61,10 @@ _lib.fwi_plan_create.argtypes = [ctypes.POINTER(fwi_problem), _P, _P, _P, ctypes
 _lib.fwi_plan_destroy.argtypes = [_P]
 _lib.fwi_forward.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_forward_noalloc.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+_lib.fwi_plan_set_loads.argtypes = [_P, ctypes.c_int32, _P, _P, _P]
+_lib.fwi_surface_traction.argtypes = [ctypes.POINTER(fwi_problem), ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, _P,
+                                      ctypes.POINTER(ctypes.c_int32)]
 _lib.fwi_misfit.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.fwi_adjoint_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
 _lib.fwi_adjoint_gradient_appb.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -92,14 +96,14 @@ _lib.fwi_adam.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _F, _F, _F, _F, ct
 _lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _P]
 _lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]
-for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
+for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_set_loads", "fwi_surface_traction", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
+EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_set_loads", "fwi_surface_traction", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
@@ -165,6 +169,36 @@ def fwi_plan_create(problem: fwi_problem, src_node, src_dir, rec_node):
                                 r.ctypes.data if r.size else None, ctypes.byref(plan)),
            what="fwi_plan_create")
     return plan
+
+
+def fwi_plan_set_loads(plan, load_src, load_node, load_vec):
+    """Host arrays: load_src int32 (n,), load_node int32 (n,), load_vec float64 (n, 3)."""
+    import numpy as np
+    s = np.ascontiguousarray(load_src, dtype=np.int32)
+    n = np.ascontiguousarray(load_node, dtype=np.int32)
+    v = np.ascontiguousarray(load_vec, dtype=np.float64).reshape(-1, 3)
+    if not (s.size == n.size == v.shape[0]):
+        raise ValueError("load_src, load_node and load_vec must have the same length")
+    _check(_lib.fwi_plan_set_loads(plan, int(s.size), s.ctypes.data if s.size else None,
+                                   n.ctypes.data if n.size else None, v.ctypes.data if v.size else None),
+           plan, "fwi_plan_set_loads")
+
+
+def fwi_surface_traction(problem: fwi_problem, xmin, xmax, ymin, ymax):
+    """(node ids, weights) of a uniform surface traction over a rectangle."""
+    import numpy as np
+    count = ctypes.c_int32()
+    st = _lib.fwi_surface_traction(ctypes.byref(problem), xmin, xmax, ymin, ymax, 0, None, None,
+                                   ctypes.byref(count))
+    if st not in (0, FWI_ERR_SHAPE):
+        _check(st, what="fwi_surface_traction")
+    node = np.zeros(count.value, np.int32)
+    weight = np.zeros(count.value, np.float64)
+    _check(_lib.fwi_surface_traction(ctypes.byref(problem), xmin, xmax, ymin, ymax, count.value,
+                                     node.ctypes.data if node.size else None,
+                                     weight.ctypes.data if weight.size else None, ctypes.byref(count)),
+           what="fwi_surface_traction")
+    return node, weight
 
 
 def fwi_plan_destroy(plan):

@@ -34,6 +34,13 @@ struct fwi_plan {
   int32_t* d_src = nullptr;
   double* d_dir = nullptr;
   int32_t* d_rec = nullptr;
+  // general nodal loads (fwi_plan_set_loads): entry e adds
+  // load_vec[e] * wavelet[load_src[e]][k] at node load_node[e]; replaces the
+  // point loads of fwi_plan_create when nload > 0
+  int nload = 0;
+  int32_t* d_load_src = nullptr;
+  int32_t* d_load_node = nullptr;
+  double* d_load_vec = nullptr;
   std::vector<double> tab;           // per-axis PML profile and 1D mass factors
   std::vector<int> fo;               // per-axis upper-face ordinals of the tile lattice
   int nface[3] = {0, 0, 0};
@@ -53,9 +60,9 @@ struct fwi_plan {
   // largest eigenvalues of M^{-1} K for the unit reference brick with lam = 1,
   // mu = 0 and lam = 0, mu = 1 (stability bound of fwi_check_model)
   double c_lam = 0.0, c_mu = 0.0;
-  double* d_info = nullptr;   // 5 doubles: device result of the model check
+  double* d_info = nullptr;   // 8 doubles: model check [0, 5), power iteration [5, 8)
   double* d_partials = nullptr;   // MISFIT_BLOCKS doubles: per-workgroup misfit sums
-  double* h_info = nullptr;       // 5 doubles of pinned host memory: the model check's result
+  double* h_info = nullptr;       // 8 doubles of pinned host memory: copy of d_info
   int device = 0;                 // device current at fwi_plan_create
   void* scratch = nullptr;        // device address of the fixed scratch array on that device
 };
@@ -319,6 +326,7 @@ int count_faces(const fwi_problem& P, const Geo& g, int d) {
 // store, no checkpoints, no gradient accumulators).
 Layout layout(const fwi_problem& P, const Geo& g, bool keep = true) {
   Layout L{};
+  keep = keep && P.ckpt_every >= 0;   // ckpt_every < 0: forward-only plan
   const int nface[3] = {count_faces(P, g, 0), count_faces(P, g, 1), count_faces(P, g, 2)};
   L.part = part_layout(g, nface, 9, true);
   L.gpart = part_layout(g, nface, 2, false);
@@ -349,7 +357,7 @@ fwi_status validate(const fwi_problem* P) {
     if (P->ne_int[d] < 1) return FWI_ERR_SHAPE;
   if (P->npml_side < 1 || P->npml_bottom < 1) return FWI_ERR_SHAPE;
   if (!(P->h > 0) || !(P->dt > 0) || P->nsteps < 1) return FWI_ERR_ARG;
-  if (P->nsrc < 1 || P->nrec < 0 || P->pml_m < 0 || P->ckpt_every < 0) return FWI_ERR_ARG;
+  if (P->nsrc < 1 || P->nrec < 0 || P->pml_m < 0 || P->ckpt_every < -1) return FWI_ERR_ARG;
   if (P->precision < FWI_FP64 || P->precision > FWI_FP32_BF16X3) return FWI_ERR_ARG;
   const double nx = 2.0 * (P->ne_int[0] + 2.0 * P->npml_side) + 1;
   const double ny = 2.0 * (P->ne_int[1] + 2.0 * P->npml_side) + 1;
@@ -430,6 +438,35 @@ __global__ void appb_force_kernel(R* __restrict__ Yout, R* __restrict__ Xn, R* _
 // then one workgroup adds the partial sums in a fixed order, so J has the same
 // bits on every run (the grid size depends only on the trace length).
 constexpr int MISFIT_BLOCKS = 2048;
+
+// General nodal loads after a nodal stage pass: the stage rate of x2 at the
+// load's node gains M^{-1} f, f = vec * wavelet(stage time); the stage
+// combination the nodal kernel applied gets that rate's share (mode 0/1:
+// Yout += cY g, acc += cA g; mode 2: Xn += cA g).  Entries are unique per
+// (source, node), so plain read-modify-writes do not race.
+template <typename R>
+__global__ void load_kernel(R* __restrict__ Yout, R* __restrict__ Xn, R* __restrict__ acc, long long reg, int sn,
+                            int mode, double cA, double cY, const R* __restrict__ invMu, int nload,
+                            const int* __restrict__ lsrc, const int* __restrict__ lnode,
+                            const double* __restrict__ lvec, const double* __restrict__ wav, int wav_len,
+                            int wav_idx) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nload) return;
+  const int src = lsrc[e], node = lnode[e];
+  const double f = wav[(size_t)src * wav_len + wav_idx];
+  const double im = (double)invMu[node];
+  const size_t off = (size_t)src * reg;
+  for (int d = 0; d < 3; ++d) {
+    const double g = im * lvec[3 * e + d] * f;
+    const size_t o = off + (size_t)(3 + d) * sn + node;
+    if (mode == 2) {
+      Xn[o] += R(cA * g);
+    } else {
+      Yout[o] += R(cY * g);
+      acc[o] += R(cA * g);
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256) misfit_kernel(const double* __restrict__ tr, const double* __restrict__ obs,
                                                      double* __restrict__ resid, long long n, int per_step,
@@ -538,6 +575,99 @@ __global__ void __launch_bounds__(1024) model_check_kernel(Geo g, const double* 
   }
   if (threadIdx.x == 0)
     for (int k = 0; k < 5; ++k) out[k] = red[k][0];
+}
+
+// Power iteration for the largest eigenvalue of M_RD^{-1} K_RD, the interior
+// stiffness over the lumped interior mass (the operator the RK4 stability
+// limit is set by; the PML stretching only adds mass).  Iterate x (x1
+// displacement of a register, source 0) was produced unscaled; with s the
+// scale stored by the previous reduction, x s has unit M_RD norm.  r = K x is
+// in the partial arrays (interior bricks only).  Per workgroup: sums of
+// x.r, m x.x and m y.y with y = r / m; writes y s to the next register.
+__device__ __forceinline__ double power_start(unsigned node, int d) {
+  // deterministic start vector in [-1, 1): integer hash of (node, component)
+  unsigned long long z = (unsigned long long)node * 3ULL + (unsigned long long)d + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) power_step_kernel(Geo g, const R* __restrict__ X, R* __restrict__ Y,
+                                                         const R* __restrict__ res, Part PT,
+                                                         const double* __restrict__ rho, int first,
+                                                         const double* __restrict__ state,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[3][256];
+  const double sc = first ? 1.0 : state[0];
+  double xr = 0.0, xm = 0.0, ym = 0.0;
+  for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < g.n_nodes; node += gridDim.x * blockDim.x) {
+    const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
+    if (is_dirichlet(g, i, j, k)) continue;
+    const int mi = interior_index(g, i, j, k);
+    if (mi < 0) continue;
+    double mrd, mp;
+    lumped_masses_tab(g, i, j, k, mrd, mp);
+    const double m = rho[mi] * mrd;
+    const PartSlots PS = part_slots(g, PT, i, j, k);
+    for (int d = 0; d < 3; ++d) {
+      const size_t o = (size_t)d * g.sn + node;
+      const double x = (double)X[o] * sc;
+      const double r = (double)gather_rows(PT, PS, res, o, d) * sc;
+      xr += x * r;
+      xm += m * x * x;
+      const double y = r / m;
+      ym += m * y * y;
+      Y[o] = R(y);
+    }
+  }
+  red[0][threadIdx.x] = xr;
+  red[1][threadIdx.x] = xm;
+  red[2][threadIdx.x] = ym;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) partials[3 * blockIdx.x + c] = red[c][0];
+}
+
+// Fixed-order sum of the partials: state[0] = scale of the next iterate
+// (1 / |y|_M), state[1] = Rayleigh quotient x.Kx / x.Mx, running maximum in state[2].
+__global__ void __launch_bounds__(256) power_reduce_kernel(const double* __restrict__ partials, int nb,
+                                                           double* __restrict__ state) {
+  __shared__ double red[3][256];
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+    for (int c = 0; c < 3; ++c) a[c] += partials[3 * b + c];
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = a[c];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double rq = red[1][0] > 0.0 ? red[0][0] / red[1][0] : 0.0;
+    state[0] = red[2][0] > 0.0 ? 1.0 / sqrt(red[2][0]) : 0.0;
+    state[1] = rq;
+    state[2] = fmax(state[2], rq);
+  }
+}
+
+// Start vector of the power iteration: deterministic values on the free
+// interior-closure nodes, zero elsewhere (x1 displacement of a register).
+template <typename R>
+__global__ void power_init_kernel(Geo g, R* __restrict__ X, double* __restrict__ state) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node == 0) state[2] = 0.0;
+  if (node >= g.n_nodes) return;
+  const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
+  const bool on = !is_dirichlet(g, i, j, k) && interior_index(g, i, j, k) >= 0;
+  for (int d = 0; d < 3; ++d) X[(size_t)d * g.sn + node] = on ? R(power_start((unsigned)node, d)) : R(0);
 }
 
 // Nodal test fields [nsrc][9][n_nodes] <-> register slot (0: x0, 1: x1, 2: x2).
@@ -726,7 +856,7 @@ struct Run {
     A.reg = (long long)L.reg_elems;
     A.cA = R(cA[s] * dt); A.cY = R(cY[s] * dt);
     A.mode = s == 0 ? 0 : (s == 3 ? 2 : 1);
-    if (wav) {
+    if (wav && p->nload == 0) {
       A.src_node = p->d_src; A.src_dir = p->d_dir; A.wav = wav;
       A.wav_len = 2 * p->prob.nsteps + 1; A.wav_idx = 2 * step + toff[s];
     }
@@ -751,6 +881,11 @@ struct Run {
         A.rot = PMLFWI_NODAL_ORDER == 1 ? (unsigned)(G.sn / 256) % nb : 0u;
         kern<<<dim3(nb, p->nsrc), 256, 0, st>>>(G, A);
       }
+    }
+    if (wav && p->nload > 0) {
+      load_kernel<R><<<blocks(p->nload, 128), 128, 0, st>>>(
+          Yout, Xn, acc, (long long)L.reg_elems, G.sn, A.mode, cA[s] * dt, cY[s] * dt, invm(), p->nload,
+          p->d_load_src, p->d_load_node, p->d_load_vec, wav, 2 * p->prob.nsteps + 1, 2 * step + toff[s]);
     }
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
@@ -806,6 +941,7 @@ struct Run {
     if ((e = zero_regs(0, 4)) != FWI_OK) return e;
     const size_t tl = (size_t)P.nsrc * (P.nsteps + 1) * p->nrec * 3;
     if ((e = fill<double>(traces, tl, 0.0)) != FWI_OK) return e;
+    keep = keep && P.ckpt_every >= 0;
     const bool keep_all = keep && P.ckpt_every == 0;
     const bool ckpts = keep && P.ckpt_every > 0;
     if (keep_all && (e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
@@ -922,6 +1058,29 @@ struct Run {
     return FWI_OK;
   }
 
+  // Largest eigenvalue of M_RD^{-1} K_RD by `iters` power iterations on the
+  // first source's registers 0 and 1 (overwritten); the result (running
+  // maximum of the Rayleigh quotients) is left in p->d_info[7].
+  fwi_status power_omega(const double* rho, const double* lam_, const double* mu_, int iters) {
+    const Geo& G = g();
+    fwi_status e;
+    if ((e = setup(rho, lam_, mu_)) != FWI_OK) return e;
+    if ((e = zero_regs(0, 2)) != FWI_OK) return e;
+    double* state = p->d_info + 5;
+    power_init_kernel<R><<<blocks(G.n_nodes, 256), 256, 0, st>>>(G, reg(0), state);
+    HIP_TRY(p, hipGetLastError());
+    const int nb = (int)std::min<size_t>(blocks(G.n_nodes, 256), MISFIT_BLOCKS / 3);
+    for (int it = 0; it < iters; ++it) {
+      R* X = reg(it & 1);
+      R* Y = reg((it + 1) & 1);
+      if ((e = elements(false, X, nullptr, 0.0, true)) != FWI_OK) return e;
+      power_step_kernel<R><<<nb, 256, 0, st>>>(G, X, Y, res(), L.part, rho, it == 0, state, p->d_partials);
+      power_reduce_kernel<<<1, 256, 0, st>>>(p->d_partials, nb, state);
+      HIP_TRY(p, hipGetLastError());
+    }
+    return FWI_OK;
+  }
+
   fwi_status apply(int which, const double* rho, const double* lam_, const double* mu_, const double* x0,
                    const double* x1, const double* x2, double* out) {
     const Geo& G = g();
@@ -943,8 +1102,19 @@ struct Run {
 
 // Model check before a solve: one small kernel, a copy of 5 doubles and a
 // stream synchronization.  info: 6 host doubles (see fwi_check_model).
+// With a workspace, a time step above the brick-by-brick bound is checked
+// again against a power-iteration estimate of the largest frequency of the
+// interior operator (that bound overestimates it by about 1.2x, enough to
+// reject the paper's own Sec. 4.1 step): accepted when dt omega_est stays 2 %
+// below the RK4 limit 2 sqrt(2).  info[4], info[5] then hold the estimate.
+constexpr int POWER_ITERS = 150;
+constexpr double POWER_MARGIN = 1.02;
+
+template <typename F>
+fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f, bool keep = true);
+
 fwi_status check_model(fwi_plan* p, hipStream_t st, const double* rho, const double* lam, const double* mu,
-                       double* info, const char* who) {
+                       double* info, const char* who, void* ws = nullptr, bool keep = true) {
   model_check_kernel<<<1, 1024, 0, st>>>(p->g, rho, lam, mu, p->c_lam, p->c_mu, p->d_info);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(p->h_info, p->d_info, 5 * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -958,22 +1128,34 @@ fwi_status check_model(fwi_plan* p, hipStream_t st, const double* rho, const dou
   for (int k = 0; k < 4; ++k) info[k] = v[k];
   info[4] = wmax;
   info[5] = wmax > 0 ? 2.0 * std::sqrt(2.0) / wmax : HUGE_VAL;
-  char msg[256];
+  char msg[320];
   if (!(v[0] > 0.0) || !(v[1] > 0.0) || !(v[2] > 0.0)) {
     std::snprintf(msg, sizeof(msg), "%s: rho, mu and 3 lam + 2 mu must be positive (min rho %g, min mu %g, "
                   "min 3 lam + 2 mu %g)", who, v[0], v[1], v[2]);
     return fail(p, FWI_ERR_ARG, msg);
   }
-  if (!(p->prob.dt <= info[5])) {
-    std::snprintf(msg, sizeof(msg), "%s: dt %.6g s above the RK4 stability bound %.6g s (omega_max %.6g 1/s)",
-                  who, p->prob.dt, info[5], wmax);
+  if (p->prob.dt <= info[5]) return FWI_OK;
+  if (ws) {
+    fwi_status s = dispatch(p, st, ws, [&](auto& r) { return r.power_omega(rho, lam, mu, POWER_ITERS); }, keep);
+    if (s != FWI_OK) return s;
+    e = hipMemcpyAsync(p->h_info + 5, p->d_info + 5, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(p, FWI_ERR_HIP, std::string(who) + ": power iteration: " + hipGetErrorString(e));
+    const double west = std::sqrt(std::max(p->h_info[7], 0.0));
+    info[4] = west;
+    info[5] = west > 0 ? 2.0 * std::sqrt(2.0) / (POWER_MARGIN * west) : HUGE_VAL;
+    if (p->prob.dt <= info[5]) return FWI_OK;
+    std::snprintf(msg, sizeof(msg), "%s: dt %.6g s above the RK4 stability bound %.6g s (power-iteration estimate "
+                  "of omega_max %.6g 1/s, brick bound %.6g 1/s)", who, p->prob.dt, info[5], west, wmax);
     return fail(p, FWI_ERR_UNSTABLE, msg);
   }
-  return FWI_OK;
+  std::snprintf(msg, sizeof(msg), "%s: dt %.6g s above the RK4 stability bound %.6g s (omega_max bound %.6g 1/s)",
+                who, p->prob.dt, info[5], wmax);
+  return fail(p, FWI_ERR_UNSTABLE, msg);
 }
 
 template <typename F>
-fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f, bool keep = true) {
+fwi_status dispatch(fwi_plan* p, hipStream_t st, void* ws, F&& f, bool keep) {
   Layout L = layout(p->prob, p->g, keep);
   if (p->prob.precision != FWI_FP64) {
     Run<float> r{p, st, L, (char*)ws};
@@ -1093,7 +1275,7 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   step("receiver nodes", (void**)&p->d_rec, rec_node, prob->nrec * sizeof(int32_t));
   step("axis tables", (void**)&p->d_tab, p->tab.data(), p->tab.size() * sizeof(double));
   step("face ordinals", (void**)&p->d_fo, p->fo.data(), p->fo.size() * sizeof(int));
-  const double zeros[5] = {0, 0, 0, 0, 0};
+  const double zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   step("model-check buffer", (void**)&p->d_info, zeros, sizeof(zeros));
   if (e == hipSuccess) {
     what = "misfit partial sums";
@@ -1109,7 +1291,7 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) {
     what = "pinned model-check result";
-    e = hipHostMalloc((void**)&p->h_info, 5 * sizeof(double), hipHostMallocDefault);
+    e = hipHostMalloc((void**)&p->h_info, 8 * sizeof(double), hipHostMallocDefault);
   }
   if (e == hipSuccess) {
     what = "device id";
@@ -1128,6 +1310,94 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   }
   *out = p;
   return FWI_OK;
+}
+
+fwi_status fwi_plan_set_loads(fwi_plan* p, int32_t nload, const int32_t* load_src, const int32_t* load_node,
+                              const double* load_vec) {
+  if (!p) return FWI_ERR_ARG;
+  if (nload < 0 || (nload > 0 && (!load_src || !load_node || !load_vec)))
+    return fail(p, FWI_ERR_ARG, "fwi_plan_set_loads: bad count or null pointer");
+  const Geo& g = p->g;
+  // merge entries of the same (source, node): the load kernel then writes each
+  // register entry from one thread
+  std::vector<std::pair<long long, int>> key(nload);
+  for (int e = 0; e < nload; ++e) {
+    const int s = load_src[e], id = load_node[e];
+    if (s < 0 || s >= p->nsrc) return fail(p, FWI_ERR_ARG, "fwi_plan_set_loads: source index out of range");
+    if (id < 0 || id >= g.n_nodes) return fail(p, FWI_ERR_ARG, "fwi_plan_set_loads: node id out of range");
+    const int k = id / g.plane, r = id - k * g.plane, j = r / g.NX, i = r - j * g.NX;
+    if (is_dirichlet(g, i, j, k)) return fail(p, FWI_ERR_ARG, "fwi_plan_set_loads: load on a Dirichlet node");
+    key[e] = {(long long)s * g.n_nodes + id, e};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> hs, hn;
+  std::vector<double> hv;
+  for (int e = 0; e < nload; ++e) {
+    const int o = key[e].second;
+    if (e == 0 || key[e].first != key[e - 1].first) {
+      hs.push_back(load_src[o]);
+      hn.push_back(load_node[o]);
+      hv.insert(hv.end(), {load_vec[3 * o], load_vec[3 * o + 1], load_vec[3 * o + 2]});
+    } else {
+      for (int d = 0; d < 3; ++d) hv[hv.size() - 3 + d] += load_vec[3 * o + d];
+    }
+  }
+  HIP_TRY(p, hipDeviceSynchronize());   // the old tables may still be in use
+  (void)hipFree(p->d_load_src);
+  (void)hipFree(p->d_load_node);
+  (void)hipFree(p->d_load_vec);
+  p->d_load_src = p->d_load_node = nullptr;
+  p->d_load_vec = nullptr;
+  p->nload = 0;
+  const int n = (int)hs.size();
+  if (n == 0) return FWI_OK;
+  HIP_TRY(p, hipMalloc((void**)&p->d_load_src, n * sizeof(int32_t)));
+  HIP_TRY(p, hipMalloc((void**)&p->d_load_node, n * sizeof(int32_t)));
+  HIP_TRY(p, hipMalloc((void**)&p->d_load_vec, 3 * n * sizeof(double)));
+  HIP_TRY(p, hipMemcpy(p->d_load_src, hs.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(p, hipMemcpy(p->d_load_node, hn.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(p, hipMemcpy(p->d_load_vec, hv.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice));
+  p->nload = n;
+  return FWI_OK;
+}
+
+fwi_status fwi_surface_traction(const fwi_problem* prob, double xmin, double xmax, double ymin, double ymax,
+                                int32_t cap, int32_t* node, double* weight, int32_t* count) {
+  if (!prob || !count || cap < 0 || (cap > 0 && (!node || !weight))) return FWI_ERR_ARG;
+  fwi_status v = validate(prob);
+  if (v != FWI_OK) return v;
+  if (!(xmin <= xmax) || !(ymin <= ymax)) return FWI_ERR_ARG;
+  const Geo g = make_geo(*prob);
+  const double h = g.h;
+  // one-dimensional weights: sum over the surface-face edges [a, a + h] inside
+  // [lo, hi] of the LGL weight of the node times h/2
+  auto axis = [&](double lo, double hi, double x0, int n, std::vector<double>& w) {
+    w.assign(n, 0.0);
+    for (int e = 0; 2 * e + 2 < n; ++e) {
+      const double a = x0 + e * h, b = a + h;
+      if (a < lo - 1e-9 * h || b > hi + 1e-9 * h) continue;
+      w[2 * e] += h / 6.0;
+      w[2 * e + 1] += 2.0 * h / 3.0;
+      w[2 * e + 2] += h / 6.0;
+    }
+  };
+  std::vector<double> wx, wy;
+  axis(xmin, xmax, g.x0, g.NX, wx);
+  axis(ymin, ymax, g.y0, g.NY, wy);
+  int32_t c = 0;
+  const int k = g.NZ - 1;
+  for (int j = 0; j < g.NY; ++j)
+    for (int i = 0; i < g.NX; ++i) {
+      const double w = wx[i] * wy[j];
+      if (w == 0.0 || is_dirichlet(g, i, j, k)) continue;
+      if (c < cap) {
+        node[c] = i + g.NX * (j + g.NY * k);
+        weight[c] = w;
+      }
+      ++c;
+    }
+  *count = c;
+  return c <= cap ? FWI_OK : FWI_ERR_SHAPE;
 }
 
 fwi_status fwi_timing_enable(fwi_plan* p, int stride) {
@@ -1172,6 +1442,9 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
   (void)hipFree(p->d_src);
   (void)hipFree(p->d_dir);
   (void)hipFree(p->d_rec);
+  (void)hipFree(p->d_load_src);
+  (void)hipFree(p->d_load_node);
+  (void)hipFree(p->d_load_vec);
   (void)hipFree(p->d_tab);
   (void)hipFree(p->d_fo);
   (void)hipFree(p->d_info);
@@ -1188,7 +1461,8 @@ fwi_status fwi_forward(fwi_plan* p, void* stream, const double* rho, const doubl
     return fail(p, FWI_ERR_ARG, "fwi_forward: null pointer");
   p->fwd_ws = nullptr;
   double info[6];
-  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_forward"); c != FWI_OK) return c;
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_forward", workspace); c != FWI_OK)
+    return c;
   fwi_status s = dispatch(p, (hipStream_t)stream, workspace,
                           [&](auto& r) { return r.forward(rho, lam, mu, wavelet, traces); });
   if (s == FWI_OK) p->fwd_ws = workspace;
@@ -1212,7 +1486,8 @@ fwi_status fwi_forward_noalloc(fwi_plan* p, void* stream, const double* rho, con
     return fail(p, FWI_ERR_ARG, msg);
   }
   double info[6];
-  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_forward_noalloc"); c != FWI_OK)
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_forward_noalloc", p->scratch,
+                                 false); c != FWI_OK)
     return c;
   // the forward registers in the plan's workspace (if any) are not touched, so
   // an fwi_adjoint_gradient after this call still sees the last fwi_forward
@@ -1247,10 +1522,13 @@ fwi_status fwi_adjoint_gradient(fwi_plan* p, void* stream, const double* rho, co
   if (!p) return FWI_ERR_ARG;
   if (!rho || !lam || !mu || !wavelet || !workspace || !g_lam || !g_mu || (p->nrec > 0 && !residual))
     return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient: null pointer");
+  if (p->prob.ckpt_every < 0)
+    return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient: forward-only plan (ckpt_every < 0) keeps nothing for an adjoint");
   if (p->fwd_ws != workspace)
     return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient: no fwi_forward on this workspace");
   double info[6];
-  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_adjoint_gradient"); c != FWI_OK) return c;
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_adjoint_gradient", workspace); c != FWI_OK)
+    return c;
   return dispatch(p, (hipStream_t)stream, workspace,
                   [&](auto& r) { return r.adjoint(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
 }
@@ -1261,10 +1539,13 @@ fwi_status fwi_adjoint_gradient_appb(fwi_plan* p, void* stream, const double* rh
   if (!p) return FWI_ERR_ARG;
   if (!rho || !lam || !mu || !wavelet || !workspace || !g_lam || !g_mu || (p->nrec > 0 && !residual))
     return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient_appb: null pointer");
+  if (p->prob.ckpt_every < 0)
+    return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient_appb: forward-only plan (ckpt_every < 0) keeps nothing for an adjoint");
   if (p->fwd_ws != workspace)
     return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient_appb: no fwi_forward on this workspace");
   double info[6];
-  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_adjoint_gradient_appb"); c != FWI_OK) return c;
+  if (fwi_status c = check_model(p, (hipStream_t)stream, rho, lam, mu, info, "fwi_adjoint_gradient_appb", workspace); c != FWI_OK)
+    return c;
   return dispatch(p, (hipStream_t)stream, workspace,
                   [&](auto& r) { return r.adjoint_appb(rho, lam, mu, wavelet, residual, g_lam, g_mu); });
 }

@@ -37,7 +37,11 @@ class Solver:
     """
 
     def __init__(self, prob, src_node, src_dir, rec_node, precision=B.FWI_FP64,
-                 ckpt_every=0, device="cuda"):
+                 ckpt_every=0, device="cuda", traction=None):
+        """traction: None (point loads src_node / src_dir), or (xmin, xmax,
+        ymin, ymax, direction) of a uniform surface traction applied by every
+        source; the wavelet is then the traction in Pa.  ckpt_every = -1 makes
+        a forward-only plan."""
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (HIP device); no CPU fallback exists")
         self.device = torch.device(device)
@@ -50,6 +54,12 @@ class Solver:
         self.nsteps = prob.nsteps
         self.plan = B.fwi_plan_create(self.problem, np.asarray(src_node), np.asarray(src_dir),
                                       np.asarray(rec_node))
+        if traction is not None:
+            xmin, xmax, ymin, ymax, direction = traction
+            node, weight = B.fwi_surface_traction(self.problem, xmin, xmax, ymin, ymax)
+            vec = weight[:, None] * np.asarray(direction, np.float64)[None, :]
+            B.fwi_plan_set_loads(self.plan, np.repeat(np.arange(self.nsrc), node.size),
+                                 np.tile(node, self.nsrc), np.tile(vec, (self.nsrc, 1)))
         nbytes = int(self.sizes.workspace_bytes)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         self.trace_shape = (self.nsrc, self.nsteps + 1, self.nrec, 3)

@@ -59,7 +59,7 @@ def test_query_sizes_match_oracle_mesh(name, make, nsrc):
 def test_query_rejects_bad_problems():
     from paper_1504_08340_amd import binding
     wl = W.tiny()
-    for field, val in (("nsteps", 0), ("npml_side", 0), ("precision", 7), ("ckpt_every", -1)):
+    for field, val in (("nsteps", 0), ("npml_side", 0), ("precision", 7), ("ckpt_every", -2)):
         p = binding.make_problem(wl.prob, 1, wl.nrec)
         setattr(p, field, val)
         with pytest.raises(binding.FwiError):

@@ -149,3 +149,50 @@ def test_misfit_is_bit_reproducible(P):
     torch.cuda.synchronize()
     assert Js[0] == Js[1] == Js[2]
     S.close()
+
+
+def _interior_omega_max(wl):
+    """Largest frequency of the interior operator M_RD^{-1} K_RD by the oracle
+    (assembled interior stiffness, lumped interior mass, scipy eigsh)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle.assemble import System
+    s = System(wl.prob, wl.rho, wl.lam, wl.mu)
+    m = s.mesh
+    nodes = np.nonzero(m.in_rd & (m.u_dof[:, 0] >= 0))[0]
+    dofs = m.u_dof[nodes].ravel()
+    K = s.Krd.tocsr()[dofs][:, dofs]
+    M = np.repeat(s.rho[nodes] * m.m_rd[nodes], 3)
+    Ms = sp.diags(1.0 / np.sqrt(M))
+    w2 = spla.eigsh((Ms @ K @ Ms).tocsr(), k=1, which="LA", return_eigenvectors=False)[0]
+    return float(np.sqrt(w2))
+
+
+def test_time_step_between_the_brick_bound_and_the_true_limit(P):
+    """A step above the brick-by-brick bound but below the true RK4 limit is
+    accepted by fwi_forward (power-iteration estimate of the largest
+    frequency); 5 % above the true limit it is rejected, and the estimate in
+    the message lies within 2 % below the oracle's exact largest frequency."""
+    import re
+    wl = W.tiny(ne_int=(3, 3, 2), npml_side=1, npml_bottom=1, nsteps=4, seed=3)
+    w_true = _interior_omega_max(wl)
+    lim = 2.0 * np.sqrt(2.0) / w_true
+    S = P.Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node)
+    info = P.fwi_check_model(S.plan, None, S.tensor(wl.rho), S.tensor(wl.lam), S.tensor(wl.mu))
+    S.close()
+    print(f"true limit {lim:.4e} s, brick bound {info[5]:.4e} s")
+    assert info[5] < 0.9 * lim
+    for scale, ok in ((0.97, True), (1.05, False)):
+        prob = wl.prob.replace(dt=scale * lim)
+        S = P.Solver(prob, wl.src_node, wl.src_dir, wl.rec_node)
+        args = [S.tensor(a) for a in (wl.rho, wl.lam, wl.mu, wl.wavelet)]
+        if ok:
+            tr = S.forward(*args)
+            assert np.isfinite(tr.cpu().numpy()).all()
+        else:
+            with pytest.raises(P.FwiError, match="power-iteration") as e:
+                S.forward(*args)
+            w_est = float(re.search(r"omega_max ([0-9.e+]+)", str(e.value)).group(1))
+            print(f"estimate {w_est:.2f}, exact {w_true:.2f}")
+            assert 0.98 * w_true <= w_est <= w_true * (1 + 1e-9)
+        S.close()

@@ -28,7 +28,7 @@ __all__ = [
     "Problem", "Workload", "node_axes", "interior_axes", "full_node_id",
     "interior_node_id", "surface_receivers", "ricker", "gaussian_pulse",
     "lame_from_velocities", "config1", "config2", "config3", "tiny",
-    "cfl_dt",
+    "cfl_dt", "TABLE1", "section41", "section43", "tiny_traction",
 ]
 
 
@@ -89,6 +89,11 @@ class Workload:
     rec_node: np.ndarray     # (nrec,) int32 full-grid node ids
     lam_true: np.ndarray | None = None   # target model (observed data)
     mu_true: np.ndarray | None = None
+    # uniform surface traction replacing the point loads, or None:
+    # (xmin, xmax, ymin, ymax) of the loaded rectangle on z = 0 and the unit
+    # direction; the wavelet then holds the traction [Pa] over time.  The
+    # nodal loads (integrals of the basis functions) are formed by each side.
+    traction: tuple | None = None
 
     @property
     def nsrc(self):
@@ -362,3 +367,79 @@ def with_model(wl, vs, rho=2000.0):
     lam_t, mu_t = _model_from_vs(np.full(vs.shape, rho), vs)
     return Workload(wl.name, wl.prob, wl.rho, wl.lam, wl.mu, wl.wavelet, wl.src_node, wl.src_dir,
                     wl.rec_node, lam_t, mu_t)
+
+
+# ----------------------------------------------------------------------------
+# the paper's Sec. 4 problems (distributed surface tractions, Gaussian pulses)
+
+# Table 1: name -> (f_max [Hz], mean [s], sigma-bar [s^2, a variance], t_end [s])
+TABLE1 = {"p20": (20.0, 0.11, 0.0014, 0.20), "p30": (30.0, 0.08, 0.0007, 0.15),
+          "p40": (40.0, 0.06, 0.0004, 0.12)}
+
+
+def _traction_workload(name, prob, lam, mu, pulse, half_region, amplitude=1000.0):
+    """One source: a vertical traction (downward, `amplitude` Pa times the
+    Gaussian pulse of Table 1) on the surface over |x|, |y| <= half_region,
+    receivers at every surface node of that region."""
+    _, mean, var, _ = TABLE1[pulse]
+    wav = sample_wavelet(lambda t: gaussian_pulse(t, mean, var), prob.dt, prob.nsteps, amplitude)[None]
+    rho = np.full(prob.n_int_nodes, 2000.0)
+    centre = np.array([_nearest_full_node(prob, (0.0, 0.0, 0.0))], np.int32)
+    down = np.array([[0.0, 0.0, -1.0]])
+    rec = surface_receivers(prob, -half_region, half_region, -half_region, half_region)
+    return Workload(name, prob, rho, lam, mu, wav, centre, down, rec,
+                    traction=(-half_region, half_region, -half_region, half_region, (0.0, 0.0, -1.0)))
+
+
+def material_28(z):
+    """(28): lam = mu = 80 + 0.45 |z| + 35 exp(-(|z| - 22.5)^2 / 150) MPa."""
+    d = np.abs(z)
+    return 1e6 * (80.0 + 0.45 * d + 35.0 * np.exp(-(d - 22.5) ** 2 / 150.0))
+
+
+def section41(pulse="p20", refined=False):
+    """Sec. 4.1 gradient check: 24 x 24 x 45 m interior, 5 m PML, 1 m bricks,
+    dt = 9e-4 s, T = 0.5 s; lam = mu from (28), rho = 2000; vertical 1 kPa
+    traction with a Table 1 pulse over |x|, |y| <= 11 m; receivers at every
+    grid point of that region.  refined: the data mesh of the same problem,
+    0.5 m bricks and dt = 4.5e-4 s (every coarse node is a node of it)."""
+    if refined:
+        prob = Problem((48, 48, 90), 10, 10, 0.5, 4.5e-4, 1112)
+    else:
+        prob = Problem((24, 24, 45), 5, 5, 1.0, 9e-4, 556)
+    _, _, gz = _interior_grid(prob)
+    lam = material_28(gz)
+    return _traction_workload(f"sec41_{pulse}{'_fine' if refined else ''}", prob, lam, lam.copy(), pulse, 11.0)
+
+
+def material_30(z):
+    """(30): layers of 80 / 101.25 / 125 MPa (lam = mu) at 0..-12, -12..-27,
+    below -27 m; a node on an interface takes the shallower layer's value."""
+    return 1e6 * np.where(z >= -12.0 - 1e-9, 80.0, np.where(z >= -27.0 - 1e-9, 101.25, 125.0))
+
+
+def section43(pulse="p20", nsteps=450, refined=False):
+    """Sec. 4.3 layered medium: 40 x 40 x 45 m interior, 6.25 m PML, 1.25 m
+    bricks, dt = 1e-3 s (T = 0.45 s for p20); target (30); start: homogeneous
+    80 MPa; 1 kPa vertical traction over |x|, |y| <= 17.5 m, receivers at
+    every grid point there.  refined: 0.625 m bricks, dt/2 (data mesh)."""
+    if refined:
+        prob = Problem((64, 64, 72), 10, 10, 0.625, 5e-4, 2 * nsteps)
+    else:
+        prob = Problem((32, 32, 36), 5, 5, 1.25, 1e-3, nsteps)
+    _, _, gz = _interior_grid(prob)
+    lam_t = material_30(gz)
+    start = np.full(prob.n_int_nodes, 80e6)
+    wl = _traction_workload(f"sec43_{pulse}{'_fine' if refined else ''}", prob, start, start.copy(), pulse, 17.5)
+    wl.lam_true, wl.mu_true = lam_t, lam_t.copy()
+    return wl
+
+
+def tiny_traction(ne_int=(4, 4, 2), npml_side=1, npml_bottom=1, nsteps=40, seed=0, half=1.0, pulse="p40"):
+    """Small heterogeneous problem with a surface traction (parity checks)."""
+    base = tiny(ne_int=ne_int, npml_side=npml_side, npml_bottom=npml_bottom, nsteps=nsteps, seed=seed)
+    _, mean, var, _ = TABLE1[pulse]
+    wav = sample_wavelet(lambda t: gaussian_pulse(t, 0.3 * mean, 0.3 * var), base.prob.dt, nsteps, 1000.0)[None]
+    return Workload("tiny_traction", base.prob, base.rho, base.lam, base.mu, wav, base.src_node[:1],
+                    np.array([[0.0, 0.0, -1.0]]), base.rec_node,
+                    traction=(-half, half, -half, half, (0.0, 0.0, -1.0)))
