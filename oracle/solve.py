@@ -48,10 +48,14 @@ class Stepper:
     ``residual_T3``, ``Minv``, ``hist``, ``mesh``, ``g`` (the assembled
     ``System`` or the element-batched ``MatFree``)."""
 
-    def __init__(self, system, src_node, src_dir, rec_node, loads=None):
+    def __init__(self, system, src_node, src_dir, rec_node, loads=None, full_gradient=False):
         """loads: optional (load_src, load_node, load_vec) list of nodal loads
         (distributed surface tractions, ``oracle.loads``) replacing the point
-        loads src_node / src_dir; the number of sources stays len(src_node)."""
+        loads src_node / src_dir; the number of sources stays len(src_node).
+        full_gradient: also differentiate the PML S-rows through the material
+        carried from the interface into the PML (chain rule of the
+        extension), instead of the interior bricks only (Sec. 3.1.3)."""
+        self.full_gradient = full_gradient
         s = system
         self.s = s
         self.dt = s.prob.dt
@@ -154,6 +158,45 @@ class Stepper:
         mat = self._mat_index()[nodes]
         np.add.at(g_lam, mat.ravel(), -pl.ravel())
         np.add.at(g_mu, mat.ravel(), -pm.ravel())
+        if self.full_gradient:
+            self._grad_pair_pml(kap, Y, g_lam, g_mu)
+
+    def _grad_pair_pml(self, kap, Y, g_lam, g_mu):
+        """PML part of g -= z^T (dA/dm) Y under the material extension.
+
+        The S-row of PML node j in brick e, (3b), is
+        -w_q [mu_j (H + H^T) + lam_j tr(H) I] with H_ik = sum_L L_kk d_k u^L_i
+        at the node's LGL point (u^L = x2, x1, x0 for L = Le, Lp, Lw), so
+        d/d lam_j = -w_q tr(H) I and d/d mu_j = -w_q (H + H^T); lam_j, mu_j
+        are the values of the interface node j projects onto (material_index),
+        which collects the sum."""
+        s = self.s
+        m = s.mesh
+        x0, x1, x2 = self.split(Y)
+        nsrc = x1.shape[1]
+        x0f = np.zeros((self.ns, nsrc))
+        x0f[s.hist] = x0
+        _, _, k2 = self.split(kap)
+        zS = m.s_nodal(s.Minv[:, None] * k2)                          # (nn, 6, nsrc)
+        fields = {"Le": m.u_nodal(x2), "Lp": m.u_nodal(x1), "Lw": m.u_nodal(x0f)}
+        el_p = np.nonzero(m.is_pml)[0]
+        mat_of = m.material_index()
+        for c0 in range(0, el_p.size, 2048):
+            nodes = m.conn[el_p[c0:c0 + 2048]]                          # (E, 27)
+            H = 0.0
+            for key, u in fields.items():
+                Lam = s.coef[key][nodes]                                 # (E, 27, 3): L_kk at the points
+                H = H + np.einsum("qak,eais->eqiks", s.g, u[nodes]) * Lam[:, :, None, :, None]
+            trH = np.einsum("eqiis->eqs", H)
+            z = zS[nodes]                                                # (E, 27, 6, nsrc)
+            dl = m.wq[None, :, None] * trH * (z[:, :, 0] + z[:, :, 1] + z[:, :, 2])
+            dm = 0.0
+            for v, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1))):
+                dm = dm + z[:, :, v] * (H[:, :, a, b] + H[:, :, b, a])
+            dm = m.wq[None, :, None] * dm
+            mat = mat_of[nodes]
+            np.add.at(g_lam, mat.ravel(), dl.sum(-1).ravel())
+            np.add.at(g_mu, mat.ravel(), dm.sum(-1).ravel())
 
     def _mat_index(self):
         if not hasattr(self, "_mi"):
