@@ -103,6 +103,15 @@ typedef struct {
                              steps and the adjoint recomputes one k-step segment
                              at a time; -1: forward-only plan (traces only,
                              no adjoint; smallest workspace) */
+  int32_t grad_full;      /* 0: the gradient of fwi_adjoint_gradient comes from
+                             the interior bricks only (Sec. 3.1.3); 1: also from
+                             the PML S-rows through the material each PML node
+                             takes from the interface node it projects onto
+                             (chain rule of that extension), so the result is
+                             the exact derivative at the interface nodes too.
+                             With 1 the stage store also keeps the PML
+                             displacement fields (9 values per PML node and
+                             stage); fwi_adjoint_gradient_appb refuses it. */
 } fwi_problem;
 
 typedef struct {
@@ -196,11 +205,13 @@ fwi_status fwi_misfit(fwi_plan* plan, void* stream, const double* traces,
  * fwi_forward on the same workspace and the same rho, lam, mu, wavelet.
  * Writes g_lam, g_mu (overwritten, summed over sources): the derivative of J
  * with respect to the nodal values on the closed interior, from the interior
- * bricks only (Sec. 3.1.3).  PML nodes take their material from the closed
- * interior box (the interface values carried outward), so on nodes of the
- * interface the full derivative of J also has PML-brick terms that this
- * restricted gradient leaves out; at every other node it is the exact
- * derivative.  Checks the model as fwi_forward does. */
+ * bricks only (Sec. 3.1.3) when the plan's grad_full is 0.  PML nodes take
+ * their material from the closed interior box (the interface values carried
+ * outward), so on nodes of the interface the full derivative of J also has
+ * PML-brick terms that this restricted gradient leaves out; at every other
+ * node it is the exact derivative.  With grad_full = 1 those terms are
+ * included (the PML S-row derivatives, summed onto the interface node each
+ * PML node projects onto).  Checks the model as fwi_forward does. */
 fwi_status fwi_adjoint_gradient(fwi_plan* plan, void* stream, const double* rho,
                                 const double* lam, const double* mu,
                                 const double* wavelet, const double* residual,

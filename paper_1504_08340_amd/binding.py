@@ -44,6 +44,7 @@ class fwi_problem(ctypes.Structure):
         ("nrec", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("ckpt_every", ctypes.c_int32),
+        ("grad_full", ctypes.c_int32),
     ]
 
 
@@ -133,7 +134,7 @@ def _check(status, plan=None, what=""):
         raise FwiError(f"{what} failed ({status}): {msg}", status)
 
 
-def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0):
+def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0, grad_full=0):
     """fwi_problem from a workloads.Problem-like object."""
     p = fwi_problem()
     p.ne_int[:] = list(prob.ne_int)
@@ -149,6 +150,7 @@ def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0):
     p.nrec = nrec
     p.precision = precision
     p.ckpt_every = ckpt_every
+    p.grad_full = int(grad_full)
     return p
 
 

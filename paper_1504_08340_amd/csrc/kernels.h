@@ -663,6 +663,126 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
   }
 }
 
+// Gradient terms of the PML S-rows under the material extension (the chain
+// rule through the interface values a PML node takes, used when the full
+// gradient is asked for).  The S-row of a PML node j in brick e carries
+// -w_q [mu_j (H + H^T) + lam_j tr(H) I], H_ik = sum_L L_kk d_k u^L_i at the
+// node's point, u^L the forward stage's (u', u, ubar) for L = (Le, Lp, Lw).
+// With z the adjoint stress at j (x1 S part of the adjoint stage register),
+// the gradient gains gw * (-w_q) (tr(H) sum_a z_aa, sum_v z_v (H_ab + H_ba))
+// at node j, summed over sources and the node's PML bricks, into the FP64
+// accumulators indexed like the partial arrays (gacc: full grid, 2 rows).
+// fwd: stored forward PML displacements of the stage, per source
+// [x1 u (3) | x2 u (3) | x0 u (3)] x sp on the PML shell.
+template <typename R, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(PMLFWI_ETHREADS)
+pml_gradient_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc, const R* __restrict__ Ybase,
+                    long long ystride, const R* __restrict__ fwd, long long fstride, double gw,
+                    double* __restrict__ gacc, Part PG) {
+  constexpr int BX = 2 * TX + 1, BY = 2 * TY + 1, BZ = 2 * TZ + 1;
+  constexpr int NB = BX * BY * BZ, NP = 27 * TX * TY * TZ;
+  static_assert(NB <= PMLFWI_ETHREADS, "one box node per thread");
+  __shared__ R sW[9][NB];
+  __shared__ R sZ[6][NB];
+  __shared__ R sG[2][NP];
+  __shared__ double sGacc[2][NB];
+
+  const int ti = xcd_tile();
+  if (ti >= ntiles) return;
+  const Tile t = tiles[ti];
+  const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
+  const size_t np = (size_t)g.sp, nn = (size_t)g.sn;
+  const R s2h = R(2.0 / g.h);
+
+  const int n = threadIdx.x;
+  const int lx = n % BX, ly = (n / BX) % BY, lz = n / (BX * BY);
+  const bool live = n < NB && lx <= 2 * cx && ly <= 2 * cy && lz <= 2 * cz;
+  const int gi = 2 * t.x + lx, gj = 2 * t.y + ly, gk = 2 * t.z + lz;
+  R Le[3] = {0, 0, 0}, Lp[3] = {0, 0, 0}, Lw[3] = {0, 0, 0};
+  bool hist = false, free_u = false;
+  size_t gnode = 0, gp = 0;
+  if (live) {
+    pml_node_setup<R>(g, gi, gj, gk, Le, Lp, Lw, hist, gnode, gp);
+    free_u = !is_dirichlet(g, gi, gj, gk);
+    sGacc[0][n] = 0.0;
+    sGacc[1][n] = 0.0;
+  }
+  for (int src = 0; src < nsrc; ++src) {
+    if (live) {
+      const R* F = fwd + (size_t)src * fstride;
+      const R* P = Ybase + (size_t)src * ystride + 6 * nn;
+      PmlNode<R> v;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        v.u1[d] = free_u ? F[d * np + gp] : R(0);
+        v.u2[d] = free_u ? F[(3 + d) * np + gp] : R(0);
+        v.u0[d] = (free_u && hist) ? F[(6 + d) * np + gp] : R(0);
+      }
+      pml_node_w<R, NB>(v, Le, Lp, Lw, n, sW);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sZ[c][n] = P[(P_X1S + c) * np + gp];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NP; q += blockDim.x) {
+      const int pt = q % 27, e = q / 27;
+      const int ea = e % TX, eb = (e / TX) % TY, ec = e / (TX * TY);
+      if (ea >= cx || eb >= cy || ec >= cz) continue;
+      const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
+      const int px = 2 * ea + qa, py = 2 * eb + qb, pz = 2 * ec + qc;
+      const int nq = px + BX * (py + BY * pz);
+      R H[3][3];
+#pragma unroll
+      for (int ii = 0; ii < 3; ++ii) {
+        R hx = 0, hy = 0, hz = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          hx += R(dlgl(qa, a)) * sW[0 + ii][(2 * ea + a) + BX * (py + BY * pz)];
+          hy += R(dlgl(qb, a)) * sW[3 + ii][px + BX * ((2 * eb + a) + BY * pz)];
+          hz += R(dlgl(qc, a)) * sW[6 + ii][px + BX * (py + BY * (2 * ec + a))];
+        }
+        H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
+      }
+      const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
+      const R z0 = sZ[0][nq], z1 = sZ[1][nq], z2 = sZ[2][nq], z3 = sZ[3][nq], z4 = sZ[4][nq], z5 = sZ[5][nq];
+      const R tr = H[0][0] + H[1][1] + H[2][2];
+      R em = 2 * (z0 * H[0][0] + z1 * H[1][1] + z2 * H[2][2]);
+      em += z3 * (H[1][2] + H[2][1]) + z4 * (H[0][2] + H[2][0]) + z5 * (H[0][1] + H[1][0]);
+      sG[0][q] = -wq * tr * (z0 + z1 + z2);
+      sG[1][q] = -wq * em;
+    }
+    __syncthreads();
+    if (live) {
+      int ox[2], oy[2], oz[2];
+      bool vx[2], vy[2], vz[2];
+      axis_bricks(lx, cx, 27, 1, ox, vx);
+      axis_bricks(ly, cy, 27 * TX, 3, oy, vy);
+      axis_bricks(lz, cz, 27 * TX * TY, 9, oz, vz);
+      R gl = 0, gm = 0;
+#pragma unroll
+      for (int a3 = 0; a3 < 2; ++a3)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int a1 = 0; a1 < 2; ++a1) {
+            if (!(vx[a1] && vy[a2] && vz[a3])) continue;
+            const int qn = ox[a1] + oy[a2] + oz[a3];
+            gl += sG[0][qn];
+            gm += sG[1][qn];
+          }
+      sGacc[0][n] += (double)gl;
+      sGacc[1][n] += (double)gm;
+    }
+    __syncthreads();
+  }
+  if (live) {
+    const int cs = (lx == 2 * cx) | ((ly == 2 * cy) << 1) | ((lz == 2 * cz) << 2);
+    const size_t o = (size_t)PG.off[cs] + part_node(g, PG, cs, gi, gj, gk), gs = (size_t)PG.size[cs];
+    const double a0 = gacc[o], a1 = gacc[o + gs];
+    gacc[o] = a0 + gw * sGacc[0][n];
+    gacc[o + gs] = a1 + gw * sGacc[1][n];
+  }
+}
+
 // Nodal part of one RK4 stage.  With r the element residual of the stage input
 // Y, the rates are K = (x1|PML, x2, M^{-1}(f - r - nodal PML terms)) and
 //   mode 0:  acc = Xn + cA K,  Yout = Xn + cY K
@@ -686,6 +806,8 @@ struct NodalArgs {
   int wav_len, wav_idx;
   R* store;                   // x1 displacement of the produced register on the
   long long store_stride;     // interior closure (per source stride), or nullptr
+  R* pstore;                  // PML displacement fields of the produced register
+  long long pstore_stride;    // [x1 u | x2 u | x0 u] x sp per source, or nullptr
   long long first, last;      // row range of this launch: [0, sn) node rows, then PML rows
   unsigned rot;               // workgroup b takes rows of block (b + rot) mod grid
 };
@@ -736,14 +858,15 @@ __device__ __forceinline__ R gather_rows(const Part& P, const PartSlots& S, cons
 }
 
 // Nodal part of one stage for node rows and PML rows; MODE as described above,
-// STORE writes the produced x1 displacement on the interior closure.
+// STORE >= 1 writes the produced x1 displacement on the interior closure,
+// STORE = 2 also the PML displacement fields (full gradient).
 // Threads [0, sn) take the displacement rows of node gid (none past n_nodes),
 // threads [sn, sn + n_pml) the PML rows; every load of a thread is issued
 // before its first store.  The accumulator is written and Xn read with
 // non-temporal hints: neither is touched again before the next stage's nodal
 // pass, so they should not displace the stage input and the residual partials
 // that the element kernels and this kernel share in the caches.
-template <typename R, int MODE, bool STORE>
+template <typename R, int MODE, int STORE>
 __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
   const unsigned blk = A.rot ? (blockIdx.x + A.rot) % gridDim.x : blockIdx.x;
@@ -801,18 +924,27 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
       for (int d = 0; d < 3; ++d)
         a2[d] -= kap * (R(c.b) * u2[d] + R(c.c) * u1[d] + R(c.d) * u0[d]);
     }
-    R out1[3];
+    R out1[3], out2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const size_t o1 = d * nn + node, o2 = (3 + d) * nn + node;
       if (MODE == 2) {
         X[o1] = out1[d] = c1[d] + cA * u2[d];
-        X[o2] = c2[d] + cA * a2[d];
+        X[o2] = out2[d] = c2[d] + cA * a2[d];
       } else {
         __builtin_nontemporal_store((MODE == 0 ? x1[d] : c1[d]) + cA * u2[d], &C[o1]);
         __builtin_nontemporal_store((MODE == 0 ? x2[d] : c2[d]) + cA * a2[d], &C[o2]);
         Yo[o1] = out1[d] = x1[d] + cY * u2[d];
-        Yo[o2] = x2[d] + cY * a2[d];
+        Yo[o2] = out2[d] = x2[d] + cY * a2[d];
+      }
+    }
+    if (STORE == 2 && pml) {
+      R* PS_ = A.pstore + (size_t)src * A.pstore_stride;
+      const size_t p = (size_t)pml_index(g, i, j, k);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        PS_[(size_t)d * np + p] = out1[d];
+        PS_[(size_t)(3 + d) * np + p] = out2[d];
       }
     }
     if (STORE) {
@@ -878,12 +1010,15 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
     if (!live) continue;
     const size_t o = (size_t)q * np + p;
+    R outv;
     if (MODE == 2) {
-      PX[o] = cv[q] + cA * rate[q];
+      PX[o] = outv = cv[q] + cA * rate[q];
     } else {
       __builtin_nontemporal_store((MODE == 0 ? xv[q] : cv[q]) + cA * rate[q], &PC[o]);
-      PO[o] = xv[q] + cY * rate[q];
+      PO[o] = outv = xv[q] + cY * rate[q];
     }
+    if (STORE == 2 && q < P_X0S)   // x0 u of a history node
+      A.pstore[(size_t)src * A.pstore_stride + (size_t)(6 + q - P_X0U) * np + p] = outv;
   }
 }
 

@@ -309,8 +309,9 @@ struct Layout {
   size_t reg_elems;   // one register, one source
   size_t res_elems;   // residual, one source
   size_t stage_elems; // stored stage displacement, all sources
+  size_t pstage_elems;// stored stage PML displacement fields, all sources (full gradient)
   int nreg, nstore, nckpt;
-  size_t off_lam, off_mu, off_invm, off_regs, off_res, off_gacc, off_store, off_ckpt, total;
+  size_t off_lam, off_mu, off_invm, off_regs, off_res, off_gacc, off_store, off_pstore, off_ckpt, total;
   Part part, gpart;
 };
 
@@ -334,6 +335,7 @@ Layout layout(const fwi_problem& P, const Geo& g, bool keep = true) {
   L.reg_elems = (size_t)U_NCOMP * g.sn + (size_t)P_NCOMP * g.sp;
   L.res_elems = 3 * (size_t)g.sn + 6 * (size_t)g.sp;
   L.stage_elems = (size_t)P.nsrc * 3 * g.si;
+  L.pstage_elems = P.grad_full ? (size_t)P.nsrc * 9 * g.sp : 0;
   const int k = P.ckpt_every;
   L.nreg = (k == 0 || !keep) ? 4 : 8;
   L.nstore = !keep ? 0 : (k == 0 ? P.nsteps : std::min(k, P.nsteps));
@@ -346,6 +348,7 @@ Layout layout(const fwi_problem& P, const Geo& g, bool keep = true) {
   L.off_res = o; o = align256(o + (size_t)P.nsrc * L.part.per_src * L.es);
   L.off_gacc = o; o = align256(o + (keep ? (size_t)L.gpart.per_src * sizeof(double) : 0));
   L.off_store = o; o = align256(o + (size_t)L.nstore * 4 * L.stage_elems * L.es);
+  L.off_pstore = o; o = align256(o + (size_t)L.nstore * 4 * L.pstage_elems * L.es);
   L.off_ckpt = o; o = align256(o + (size_t)L.nckpt * P.nsrc * L.reg_elems * L.es);
   L.total = o;
   return L;
@@ -359,6 +362,7 @@ fwi_status validate(const fwi_problem* P) {
   if (!(P->h > 0) || !(P->dt > 0) || P->nsteps < 1) return FWI_ERR_ARG;
   if (P->nsrc < 1 || P->nrec < 0 || P->pml_m < 0 || P->ckpt_every < -1) return FWI_ERR_ARG;
   if (P->precision < FWI_FP64 || P->precision > FWI_FP32_BF16X3) return FWI_ERR_ARG;
+  if (P->grad_full != 0 && P->grad_full != 1) return FWI_ERR_ARG;
   const double nx = 2.0 * (P->ne_int[0] + 2.0 * P->npml_side) + 1;
   const double ny = 2.0 * (P->ne_int[1] + 2.0 * P->npml_side) + 1;
   const double nz = 2.0 * (P->ne_int[2] + P->npml_bottom) + 1;
@@ -512,6 +516,63 @@ __global__ void extract_kernel(Geo g, const R* __restrict__ X, long long reg, R*
   const size_t node = (size_t)(jx + 2 * g.ps) + (size_t)g.NX * ((jy + 2 * g.ps) + (size_t)g.NY * (jz + 2 * g.pb));
   for (int d = 0; d < 3; ++d)
     S[(size_t)src * sstr + (size_t)d * g.si + mi] = X[(size_t)src * reg + (size_t)d * g.sn + node];
+}
+
+// PML displacement fields of a register -> stored-stage slot [x1 u | x2 u | x0 u] x sp
+// (zero on Dirichlet nodes; x0 u only on history nodes).
+template <typename R>
+__global__ void pextract_kernel(Geo g, const R* __restrict__ X, long long reg, R* __restrict__ S, long long sstr) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, src = blockIdx.y;
+  if (p >= g.n_pml) return;
+  int i, j, k;
+  pml_coords(g, p, i, j, k);
+  const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
+  const R* U = X + (size_t)src * reg;
+  const R* P = U + 6 * (size_t)g.sn;
+  R* D = S + (size_t)src * sstr;
+  const bool dir = is_dirichlet(g, i, j, k);
+  const bool hist = !dir && pml_coef_tab(g, i, j, k).nbeta >= 2;
+  for (int d = 0; d < 3; ++d) {
+    D[(size_t)d * g.sp + p] = dir ? R(0) : U[(size_t)d * g.sn + node];
+    D[(size_t)(3 + d) * g.sp + p] = dir ? R(0) : U[(size_t)(3 + d) * g.sn + node];
+    D[(size_t)(6 + d) * g.sp + p] = hist ? P[(size_t)(P_X0U + d) * g.sp + p] : R(0);
+  }
+}
+
+// g = sum over the PML and interior nodes that take their material from
+// interior node mi (the node itself and, on the interface, the PML nodes that
+// project onto it) of the accumulator slots that can hold a contribution.
+__global__ void gradient_reduce_full_kernel(Geo g, const double* __restrict__ gacc, Part PG,
+                                            double* __restrict__ g_lam, double* __restrict__ g_mu) {
+  const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mi >= g.n_int) return;
+  const int jz = mi / (g.NIX * g.NIY), rr = mi - jz * g.NIX * g.NIY, jy = rr / g.NIX, jx = rr - jy * g.NIX;
+  auto range = [](int jm, int n_int, int off, int n_full, int& lo, int& hi) {
+    lo = jm + off;
+    hi = jm + off;
+    if (jm == 0) lo = 0;
+    if (jm == n_int - 1) hi = n_full - 1;
+  };
+  int i0, i1, j0, j1, k0, k1;
+  range(jx, g.NIX, 2 * g.ps, g.NX, i0, i1);
+  range(jy, g.NIY, 2 * g.ps, g.NY, j0, j1);
+  range(jz, g.NIZ, 2 * g.pb, g.NZ, k0, k1);
+  double a = 0.0, b = 0.0;
+  for (int k = k0; k <= k1; ++k)
+    for (int j = j0; j <= j1; ++j)
+      for (int i = i0; i <= i1; ++i) {
+        const int mask = face_mask(g, i, j, k);
+        size_t o = (size_t)PG.off[0] + part_node(g, PG, 0, i, j, k);
+        a += gacc[o];
+        b += gacc[o + PG.size[0]];
+        for (int c = mask; c; c = (c - 1) & mask) {
+          o = (size_t)PG.off[c] + part_node(g, PG, c, i, j, k);
+          a += gacc[o];
+          b += gacc[o + PG.size[c]];
+        }
+      }
+  g_lam[mi] = a;
+  g_mu[mi] = b;
 }
 
 // g = sum of the gradient accumulator slots that can hold a contribution.
@@ -750,6 +811,9 @@ struct Run {
   R* reg(int r) const { return (R*)(ws + L.off_regs) + (size_t)r * p->nsrc * L.reg_elems; }
   R* res() const { return (R*)(ws + L.off_res); }
   double* gacc() const { return (double*)(ws + L.off_gacc); }
+  R* pstore(int nl, int s) const {
+    return L.pstage_elems ? (R*)(ws + L.off_pstore) + ((size_t)nl * 4 + s) * L.pstage_elems : nullptr;
+  }
   R* store(int nl, int s) const {
     return (R*)(ws + L.off_store) + ((size_t)nl * 4 + s) * L.stage_elems;
   }
@@ -804,7 +868,8 @@ struct Run {
           g(), p->d_tiles_pml, nt, p->nsrc, Y, reg, lam(), mu(), res(), L.part);
   }
 
-  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw, bool interior_only = false) {
+  fwi_status elements(bool adj, const R* Y, const R* fwd, double gw, bool interior_only = false,
+                      const R* pfwd = nullptr) {
     const Geo& G = g();
     const long long reg = (long long)L.reg_elems;
     const int ns = p->nsrc;
@@ -839,12 +904,20 @@ struct Run {
         launch_pml<PML_ALL>(adj, grid, nt, Y, reg);
       }
     }
+    if (pml && pfwd) {
+      // S-row terms of the gradient under the material extension; gacc slots
+      // differ from the interior launch's, so the two may overlap
+      const int nt = (int)p->tiles_pml.size();
+      pml_gradient_kernel<R, TX, TY, TZ><<<8u * (unsigned)((nt + 7) / 8), ETHREADS, 0, st>>>(
+          G, p->d_tiles_pml, nt, ns, Y, reg, pfwd, (long long)(9LL * G.sp), gw, gacc(), L.gpart);
+    }
     if (fork) HIP_TRY(p, hipStreamWaitEvent(st, p->join_ev, 0));
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
 
-  fwi_status nodal(int s, R* Yin, R* Yout, R* Xn, R* acc, const double* wav, int step, R* store) {
+  fwi_status nodal(int s, R* Yin, R* Yout, R* Xn, R* acc, const double* wav, int step, R* store,
+                   R* pstore_ = nullptr) {
     static const double cA[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
     static const double cY[4] = {0.5, 0.5, 1.0, 0.0};
     static const int toff[4] = {0, 1, 1, 2};
@@ -861,12 +934,17 @@ struct Run {
       A.wav_len = 2 * p->prob.nsteps + 1; A.wav_idx = 2 * step + toff[s];
     }
     A.store = store; A.store_stride = 3LL * G.si;
+    A.pstore = store ? pstore_ : nullptr; A.pstore_stride = 9LL * G.sp;
     const long long rows = (long long)G.sn + G.n_pml;
     {
       TimedLaunch tl(p, FWI_K_NODAL, st);
-      auto kern = A.mode == 0 ? (store ? nodal_rk_kernel<R, 0, true> : nodal_rk_kernel<R, 0, false>)
-                : A.mode == 1 ? (store ? nodal_rk_kernel<R, 1, true> : nodal_rk_kernel<R, 1, false>)
-                              : (store ? nodal_rk_kernel<R, 2, true> : nodal_rk_kernel<R, 2, false>);
+      const int sm = !store ? 0 : (A.pstore ? 2 : 1);
+      using K = void (*)(Geo, NodalArgs<R>);
+      static const K table[3][3] = {
+          {nodal_rk_kernel<R, 0, 0>, nodal_rk_kernel<R, 0, 1>, nodal_rk_kernel<R, 0, 2>},
+          {nodal_rk_kernel<R, 1, 0>, nodal_rk_kernel<R, 1, 1>, nodal_rk_kernel<R, 1, 2>},
+          {nodal_rk_kernel<R, 2, 0>, nodal_rk_kernel<R, 2, 1>, nodal_rk_kernel<R, 2, 2>}};
+      const K kern = table[A.mode][sm];
       if (PMLFWI_NODAL_ORDER == 2) {
         A.first = 0;
         A.last = G.sn;
@@ -905,14 +983,21 @@ struct Run {
     R* outs[4] = {Ya, Yb, Ya, nullptr};
     for (int s = 0; s < 4; ++s) {
       const R* fwd = fwd_nl >= 0 ? store(fwd_nl, 3 - s) : nullptr;
-      fwi_status e = elements(adj, in, fwd, -bw[s] * p->prob.dt);
+      const R* pfwd = fwd_nl >= 0 ? pstore(fwd_nl, 3 - s) : nullptr;
+      fwi_status e = elements(adj, in, fwd, -bw[s] * p->prob.dt, false, pfwd);
       if (e != FWI_OK) return e;
       R* st_ = nullptr;
+      R* pst_ = nullptr;
       if (store_nl >= 0) {
-        if (s < 3) st_ = store(store_nl, s + 1);
-        else if (store_next) st_ = store(store_nl + 1, 0);
+        if (s < 3) {
+          st_ = store(store_nl, s + 1);
+          pst_ = pstore(store_nl, s + 1);
+        } else if (store_next) {
+          st_ = store(store_nl + 1, 0);
+          pst_ = pstore(store_nl + 1, 0);
+        }
       }
-      e = nodal(s, in, outs[s], Xn, acc, wav, n, st_);
+      e = nodal(s, in, outs[s], Xn, acc, wav, n, st_, pst_);
       if (e != FWI_OK) return e;
       in = outs[s];
     }
@@ -925,9 +1010,15 @@ struct Run {
     return fill<R>(res(), (size_t)p->nsrc * L.part.per_src, R(0));
   }
 
-  fwi_status extract(const R* X, R* S) {
+  // Stage-store slot from a register: interior x1 displacement, and with the
+  // full gradient the PML displacement fields (slot (nl, s)).
+  fwi_status extract(const R* X, int nl, int s) {
     const Geo& G = g();
-    extract_kernel<R><<<dim3(blocks(G.n_int, 256), p->nsrc), 256, 0, st>>>(G, X, (long long)L.reg_elems, S, 3LL * G.si);
+    extract_kernel<R><<<dim3(blocks(G.n_int, 256), p->nsrc), 256, 0, st>>>(G, X, (long long)L.reg_elems,
+                                                                          store(nl, s), 3LL * G.si);
+    if (R* ps = pstore(nl, s))
+      pextract_kernel<R><<<dim3(blocks(G.n_pml, 256), p->nsrc), 256, 0, st>>>(G, X, (long long)L.reg_elems, ps,
+                                                                             9LL * G.sp);
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
@@ -944,7 +1035,7 @@ struct Run {
     keep = keep && P.ckpt_every >= 0;
     const bool keep_all = keep && P.ckpt_every == 0;
     const bool ckpts = keep && P.ckpt_every > 0;
-    if (keep_all && (e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
+    if (keep_all && (e = extract(reg(0), 0, 0)) != FWI_OK) return e;
     for (int n = 0; n < P.nsteps; ++n) {
       if (ckpts && n % P.ckpt_every == 0)
         HIP_TRY(p, hipMemcpyAsync(ckpt(n / P.ckpt_every), reg(0), (size_t)P.nsrc * L.reg_elems * L.es,
@@ -988,7 +1079,7 @@ struct Run {
       if (!keep_all) {
         HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(sg), (size_t)P.nsrc * L.reg_elems * L.es,
                                   hipMemcpyDeviceToDevice, st));
-        if ((e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
+        if ((e = extract(reg(0), 0, 0)) != FWI_OK) return e;
         for (int n = a; n < b; ++n)
           if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
       }
@@ -997,7 +1088,10 @@ struct Run {
         if (n > 0 && (e = impulse(ra, resid, n)) != FWI_OK) return e;
       }
     }
-    gradient_reduce_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
+    if (p->prob.grad_full)
+      gradient_reduce_full_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
+    else
+      gradient_reduce_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
@@ -1028,7 +1122,7 @@ struct Run {
       if (!keep_all) {
         HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(sg), (size_t)P.nsrc * L.reg_elems * L.es,
                                   hipMemcpyDeviceToDevice, st));
-        if ((e = extract(reg(0), store(0, 0))) != FWI_OK) return e;
+        if ((e = extract(reg(0), 0, 0)) != FWI_OK) return e;
         for (int n = a; n < b; ++n)
           if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
       }
@@ -1539,6 +1633,9 @@ fwi_status fwi_adjoint_gradient_appb(fwi_plan* p, void* stream, const double* rh
   if (!p) return FWI_ERR_ARG;
   if (!rho || !lam || !mu || !wavelet || !workspace || !g_lam || !g_mu || (p->nrec > 0 && !residual))
     return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient_appb: null pointer");
+  if (p->prob.grad_full)
+    return fail(p, FWI_ERR_ARG, "fwi_adjoint_gradient_appb: the full gradient (grad_full = 1) is built for the "
+                                "exact adjoint only");
   if (p->prob.ckpt_every < 0)
     return fail(p, FWI_ERR_STATE, "fwi_adjoint_gradient_appb: forward-only plan (ckpt_every < 0) keeps nothing for an adjoint");
   if (p->fwd_ws != workspace)
