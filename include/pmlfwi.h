@@ -112,6 +112,12 @@ typedef struct {
                              With 1 the stage store also keeps the PML
                              displacement fields (9 values per PML node and
                              stage); fwi_adjoint_gradient_appb refuses it. */
+  int32_t ckpt_slots;     /* with ckpt_every = k > 0: 0 keeps the full state at
+                             every segment start (ceil(N/k) states); c > 0 keeps
+                             at most c states and recomputes by binomial
+                             checkpointing over the segments (revolve
+                             schedules: the least number of segment advances
+                             for c slots).  Must be 0 when ckpt_every <= 0. */
 } fwi_problem;
 
 typedef struct {
@@ -127,6 +133,10 @@ typedef struct {
   int64_t tiles_interior; /* element tiles over the interior bricks (ragged ones included) */
   int64_t tiles_pml;      /* element tiles over the PML bricks */
   int64_t element_threads;/* threads of an element-kernel workgroup */
+  int64_t ckpt_states;    /* full states the workspace holds (checkpoint slots) */
+  int64_t schedule_advances; /* segment advances of the checkpoint schedule
+                             (forward sweep to its checkpoints + adjoint) */
+  int64_t adjoint_forward_steps; /* forward RK4 steps the adjoint recomputes */
 } fwi_sizes;
 
 typedef struct fwi_plan fwi_plan;

@@ -45,6 +45,7 @@ class fwi_problem(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("ckpt_every", ctypes.c_int32),
         ("grad_full", ctypes.c_int32),
+        ("ckpt_slots", ctypes.c_int32),
     ]
 
 
@@ -52,7 +53,8 @@ class fwi_sizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "n_nodes", "n_int_nodes", "n_pml_nodes", "n_state", "n_hist", "trace_len",
         "workspace_bytes", "register_bytes")] + [("tile", ctypes.c_int64 * 3)] + [
-        (n, ctypes.c_int64) for n in ("tiles_interior", "tiles_pml", "element_threads")]
+        (n, ctypes.c_int64) for n in ("tiles_interior", "tiles_pml", "element_threads", "ckpt_states",
+                                      "schedule_advances", "adjoint_forward_steps")]
 
 
 _P = ctypes.c_void_p
@@ -134,7 +136,7 @@ def _check(status, plan=None, what=""):
         raise FwiError(f"{what} failed ({status}): {msg}", status)
 
 
-def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0, grad_full=0):
+def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0, grad_full=0, ckpt_slots=0):
     """fwi_problem from a workloads.Problem-like object."""
     p = fwi_problem()
     p.ne_int[:] = list(prob.ne_int)
@@ -151,6 +153,7 @@ def make_problem(prob, nsrc, nrec, precision=FWI_FP64, ckpt_every=0, grad_full=0
     p.precision = precision
     p.ckpt_every = ckpt_every
     p.grad_full = int(grad_full)
+    p.ckpt_slots = int(ckpt_slots)
     return p
 
 

@@ -24,6 +24,130 @@ using namespace pmlfwi;
 // Message of the last failed fwi_plan_create on this thread (no plan to hold it).
 static thread_local std::string g_plan_err;
 
+namespace {
+// ---------------------------------------------------------------- checkpoint schedules
+// With checkpoint spacing k the N steps fall into nseg segments; the adjoint
+// reverses them last to first, recomputing each from the full state at its
+// start (kept in a checkpoint slot) with the stage stores on.
+//  * slots = 0: the forward keeps the state at every segment start.
+//  * slots = c > 0: binomial checkpointing over the segments with c slots
+//    (Griewank's "revolve" schedules, Griewank and Walther, ACM TOMS 26,
+//    2000): reversing l segments from a held state with s free slots, advance
+//    m segments, keep the state there, reverse the right part with s - 1
+//    slots, then the left part with s.  The least total number of segment
+//    advances has a closed form (revolve_cost); the split m is the first
+//    that attains it.  The forward sweep already performs the first chain of
+//    advances and keeps those states, so the adjoint starts at the last
+//    segment.
+enum ActKind { ACT_LOAD = 0, ACT_ADVANCE = 1, ACT_SAVE = 2, ACT_REVERSE = 3 };
+struct Act {
+  int kind, a, b;   // LOAD slot a (-1: the state at rest); ADVANCE segments a -> b;
+                    // SAVE slot a; REVERSE segment a
+};
+
+// C(S + t, S), saturating above `cap`.
+long long binom_capped(int S, long long t, long long cap) {
+  long double b = 1.0L;
+  for (long long i = 1; i <= t; ++i) {
+    b = b * (long double)(S + i) / (long double)i;
+    if (b > (long double)cap) return cap + 1;
+  }
+  return (long long)(b + 0.5L);
+}
+
+// Least number of segment advances that reverse l segments from a held state
+// with s free slots: 0 for l <= 1, l (l - 1) / 2 with no slot, else with
+// S = s + 1 snapshots and t the least integer with C(S + t, S) >= l,
+// t l - C(S + t, S + 1).
+long long revolve_cost(long long l, int s) {
+  if (l <= 1) return 0;
+  if (s == 0) return l * (l - 1) / 2;
+  const int S = s + 1;
+  long long t = 0;
+  while (binom_capped(S, t, l) < l) ++t;
+  return t * l - binom_capped(S + 1, t - 1, (long long)1 << 62);
+}
+
+int revolve_split(int l, int s) {
+  const long long best = revolve_cost(l, s);
+  for (int m = 1; m < l; ++m)
+    if (m + revolve_cost(l - m, s - 1) + revolve_cost(m, s) == best) return m;
+  return 1;
+}
+
+void revolve_gen(int first, int last, int s, int src, bool pre, int slots, std::vector<Act>& out,
+                 std::vector<int>& fwd_slot) {
+  const int l = last - first;
+  if (l == 1) {
+    out.push_back({ACT_LOAD, src, 0});
+    out.push_back({ACT_REVERSE, first, 0});
+    return;
+  }
+  if (s == 0) {
+    for (int j = l - 1; j >= 0; --j) {
+      out.push_back({ACT_LOAD, src, 0});
+      if (j > 0) out.push_back({ACT_ADVANCE, first, first + j});
+      out.push_back({ACT_REVERSE, first + j, 0});
+    }
+    return;
+  }
+  const int m = revolve_split(l, s);
+  const int slot = slots - s;
+  if (pre) {
+    fwd_slot[first + m] = slot;
+  } else {
+    out.push_back({ACT_LOAD, src, 0});
+    out.push_back({ACT_ADVANCE, first, first + m});
+    out.push_back({ACT_SAVE, slot, 0});
+  }
+  revolve_gen(first + m, last, s - 1, slot, pre, slots, out, fwd_slot);
+  revolve_gen(first, first + m, s, src, false, slots, out, fwd_slot);
+}
+
+struct Schedule {
+  std::vector<Act> acts;       // adjoint actions
+  std::vector<int> fwd_slot;   // per segment start: slot the forward keeps it in, or -1
+  int nseg = 0, slots = 0;     // slots actually used
+  long long advances = 0;      // segment advances of forward chain + adjoint
+  long long adjoint_steps = 0; // forward steps the adjoint recomputes
+};
+
+Schedule make_schedule(const fwi_problem& P) {
+  Schedule S;
+  const int k = P.ckpt_every;
+  if (k <= 0) return S;
+  S.nseg = (P.nsteps + k - 1) / k;
+  S.fwd_slot.assign(S.nseg, -1);
+  if (P.ckpt_slots == 0 || P.ckpt_slots >= S.nseg - 1) {
+    // a slot for every segment start (segment 0: the state at rest)
+    S.slots = S.nseg;
+    for (int g = 0; g < S.nseg; ++g) S.fwd_slot[g] = g;
+    for (int g = S.nseg - 1; g >= 0; --g) {
+      S.acts.push_back({ACT_LOAD, g, 0});
+      S.acts.push_back({ACT_REVERSE, g, 0});
+    }
+  } else {
+    S.slots = P.ckpt_slots;
+    revolve_gen(0, S.nseg, P.ckpt_slots, -1, true, P.ckpt_slots, S.acts, S.fwd_slot);
+  }
+  auto seg_len = [&](int g) { return std::min(P.nsteps, (g + 1) * k) - g * k; };
+  long long chain = 0;
+  for (int g = 1; g < S.nseg; ++g)
+    if (S.fwd_slot[g] >= 0) chain = g;
+  S.advances = chain;
+  for (const Act& a : S.acts) {
+    if (a.kind == ACT_ADVANCE) {
+      S.advances += a.b - a.a;
+      for (int g = a.a; g < a.b; ++g) S.adjoint_steps += seg_len(g);
+    } else if (a.kind == ACT_REVERSE) {
+      S.adjoint_steps += seg_len(a.a);
+    }
+  }
+  return S;
+}
+
+}  // namespace
+
 struct fwi_plan {
   fwi_problem prob;
   Geo g;
@@ -64,6 +188,7 @@ struct fwi_plan {
   double* d_partials = nullptr;   // MISFIT_BLOCKS doubles: per-workgroup misfit sums
   double* h_info = nullptr;       // 8 doubles of pinned host memory: copy of d_info
   int device = 0;                 // device current at fwi_plan_create
+  Schedule sched;                 // checkpoint schedule (ckpt_every > 0)
   void* scratch = nullptr;        // device address of the fixed scratch array on that device
 };
 
@@ -339,7 +464,12 @@ Layout layout(const fwi_problem& P, const Geo& g, bool keep = true) {
   const int k = P.ckpt_every;
   L.nreg = (k == 0 || !keep) ? 4 : 8;
   L.nstore = !keep ? 0 : (k == 0 ? P.nsteps : std::min(k, P.nsteps));
-  L.nckpt = (k == 0 || !keep) ? 0 : (P.nsteps + k - 1) / k;
+  if (k > 0 && keep) {
+    const int nseg = (P.nsteps + k - 1) / k;
+    L.nckpt = (P.ckpt_slots == 0 || P.ckpt_slots >= nseg - 1) ? nseg : P.ckpt_slots;
+  } else {
+    L.nckpt = 0;
+  }
   size_t o = 0;
   L.off_lam = o; o = align256(o + (size_t)g.n_int * L.es);
   L.off_mu = o; o = align256(o + (size_t)g.n_int * L.es);
@@ -363,6 +493,7 @@ fwi_status validate(const fwi_problem* P) {
   if (P->nsrc < 1 || P->nrec < 0 || P->pml_m < 0 || P->ckpt_every < -1) return FWI_ERR_ARG;
   if (P->precision < FWI_FP64 || P->precision > FWI_FP32_BF16X3) return FWI_ERR_ARG;
   if (P->grad_full != 0 && P->grad_full != 1) return FWI_ERR_ARG;
+  if (P->ckpt_slots < 0 || (P->ckpt_slots > 0 && P->ckpt_every <= 0)) return FWI_ERR_ARG;
   const double nx = 2.0 * (P->ne_int[0] + 2.0 * P->npml_side) + 1;
   const double ny = 2.0 * (P->ne_int[1] + 2.0 * P->npml_side) + 1;
   const double nz = 2.0 * (P->ne_int[2] + P->npml_bottom) + 1;
@@ -1037,9 +1168,9 @@ struct Run {
     const bool ckpts = keep && P.ckpt_every > 0;
     if (keep_all && (e = extract(reg(0), 0, 0)) != FWI_OK) return e;
     for (int n = 0; n < P.nsteps; ++n) {
-      if (ckpts && n % P.ckpt_every == 0)
-        HIP_TRY(p, hipMemcpyAsync(ckpt(n / P.ckpt_every), reg(0), (size_t)P.nsrc * L.reg_elems * L.es,
-                                  hipMemcpyDeviceToDevice, st));
+      if (ckpts && n % P.ckpt_every == 0 && p->sched.fwd_slot[n / P.ckpt_every] >= 0)
+        HIP_TRY(p, hipMemcpyAsync(ckpt(p->sched.fwd_slot[n / P.ckpt_every]), reg(0),
+                                  (size_t)P.nsrc * L.reg_elems * L.es, hipMemcpyDeviceToDevice, st));
       if ((e = step(false, 0, n, wav, keep_all ? n : -1, n + 1 < P.nsteps, -1)) != FWI_OK)
         return e;
       if (p->nrec > 0) {
@@ -1061,6 +1192,37 @@ struct Run {
     return FWI_OK;
   }
 
+  // Runs the checkpoint schedule; reverse(a, b) performs the adjoint steps
+  // b-1 .. a once the stage store holds the segment [a, b) (slot n - a).
+  template <typename F>
+  fwi_status run_schedule(const double* wav, F&& reverse) {
+    const fwi_problem& P = p->prob;
+    const int k = P.ckpt_every;
+    const size_t bytes = (size_t)P.nsrc * L.reg_elems * L.es;
+    fwi_status e;
+    for (const Act& act : p->sched.acts) {
+      if (act.kind == ACT_LOAD) {
+        if (act.a < 0) {
+          if ((e = fill<R>(reg(0), (size_t)P.nsrc * L.reg_elems, R(0))) != FWI_OK) return e;
+        } else {
+          HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(act.a), bytes, hipMemcpyDeviceToDevice, st));
+        }
+      } else if (act.kind == ACT_SAVE) {
+        HIP_TRY(p, hipMemcpyAsync(ckpt(act.a), reg(0), bytes, hipMemcpyDeviceToDevice, st));
+      } else if (act.kind == ACT_ADVANCE) {
+        for (int n = act.a * k; n < std::min(P.nsteps, act.b * k); ++n)
+          if ((e = step(false, 0, n, wav, -1, false, -1)) != FWI_OK) return e;
+      } else {
+        const int a = act.a * k, b = std::min(P.nsteps, a + k);
+        if ((e = extract(reg(0), 0, 0)) != FWI_OK) return e;
+        for (int n = a; n < b; ++n)
+          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
+        if ((e = reverse(a, b)) != FWI_OK) return e;
+      }
+    }
+    return FWI_OK;
+  }
+
   fwi_status adjoint(const double* rho, const double* lam_, const double* mu_, const double* wav,
                      const double* resid, double* gl, double* gm) {
     const fwi_problem& P = p->prob;
@@ -1072,21 +1234,18 @@ struct Run {
     const int ra = keep_all ? 0 : 4;          // adjoint registers
     if ((e = zero_regs(ra, 4)) != FWI_OK) return e;
     if ((e = impulse(ra, resid, P.nsteps)) != FWI_OK) return e;
-    const int k = keep_all ? P.nsteps : P.ckpt_every;
-    const int nseg = (P.nsteps + k - 1) / k;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
-      const int a = sg * k, b = std::min(P.nsteps, a + k);
-      if (!keep_all) {
-        HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(sg), (size_t)P.nsrc * L.reg_elems * L.es,
-                                  hipMemcpyDeviceToDevice, st));
-        if ((e = extract(reg(0), 0, 0)) != FWI_OK) return e;
-        for (int n = a; n < b; ++n)
-          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
-      }
+    auto reverse = [&](int a, int b) -> fwi_status {
+      fwi_status e2;
       for (int n = b - 1; n >= a; --n) {
-        if ((e = step(true, ra, n, nullptr, -1, false, n - a)) != FWI_OK) return e;
-        if (n > 0 && (e = impulse(ra, resid, n)) != FWI_OK) return e;
+        if ((e2 = step(true, ra, n, nullptr, -1, false, n - a)) != FWI_OK) return e2;
+        if (n > 0 && (e2 = impulse(ra, resid, n)) != FWI_OK) return e2;
       }
+      return FWI_OK;
+    };
+    if (keep_all) {
+      if ((e = reverse(0, P.nsteps)) != FWI_OK) return e;
+    } else if ((e = run_schedule(wav, reverse)) != FWI_OK) {
+      return e;
     }
     if (p->prob.grad_full)
       gradient_reduce_full_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
@@ -1115,24 +1274,15 @@ struct Run {
     const bool keep_all = P.ckpt_every == 0;
     const int ra = keep_all ? 0 : 4;
     if ((e = zero_regs(ra, 4)) != FWI_OK) return e;
-    const int k = keep_all ? P.nsteps : P.ckpt_every;
-    const int nseg = (P.nsteps + k - 1) / k;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
-      const int a = sg * k, b = std::min(P.nsteps, a + k);
-      if (!keep_all) {
-        HIP_TRY(p, hipMemcpyAsync(reg(0), ckpt(sg), (size_t)P.nsrc * L.reg_elems * L.es,
-                                  hipMemcpyDeviceToDevice, st));
-        if ((e = extract(reg(0), 0, 0)) != FWI_OK) return e;
-        for (int n = a; n < b; ++n)
-          if ((e = step(false, 0, n, wav, n - a, n + 1 < b, -1)) != FWI_OK) return e;
-      }
+    auto reverse = [&](int a, int b) -> fwi_status {
+      fwi_status e2 = FWI_OK;
       for (int n = b - 1; n >= a; --n) {
         R* Xn = reg(ra);
         R* outs[4] = {reg(ra + 1), reg(ra + 2), reg(ra + 1), nullptr};
         R* in = Xn;
         for (int s = 0; s < 4; ++s) {
-          if ((e = elements(true, in, nullptr, 0.0)) != FWI_OK) return e;
-          if ((e = nodal(s, in, outs[s], Xn, reg(ra + 3), nullptr, n, nullptr)) != FWI_OK) return e;
+          if ((e2 = elements(true, in, nullptr, 0.0)) != FWI_OK) return e2;
+          if ((e2 = nodal(s, in, outs[s], Xn, reg(ra + 3), nullptr, n, nullptr)) != FWI_OK) return e2;
           if (p->nrec > 0) {
             const int mode = s == 0 ? 0 : (s == 3 ? 2 : 1);
             const double ah = s == 0 ? 1.0 : (s == 3 ? 0.0 : 0.5), al = 1.0 - ah;
@@ -1144,8 +1294,14 @@ struct Run {
           in = outs[s];
         }
         const double w = (n == 0 || n == P.nsteps) ? 0.5 : 1.0;
-        if ((e = elements(true, Xn, store(n - a, 0), dt * w, true)) != FWI_OK) return e;
+        if ((e2 = elements(true, Xn, store(n - a, 0), dt * w, true)) != FWI_OK) return e2;
       }
+      return e2;
+    };
+    if (keep_all) {
+      if ((e = reverse(0, P.nsteps)) != FWI_OK) return e;
+    } else if ((e = run_schedule(wav, reverse)) != FWI_OK) {
+      return e;
     }
     gradient_reduce_kernel<<<blocks(G.n_int, 256), 256, 0, st>>>(G, gacc(), L.gpart, gl, gm);
     HIP_TRY(p, hipGetLastError());
@@ -1319,6 +1475,10 @@ fwi_status fwi_query(const fwi_problem* prob, fwi_sizes* out) {
   out->tiles_interior = ix * iy * iz;
   out->tiles_pml = nx * ny * nz - ix * iy * iz;
   out->element_threads = ETHREADS;
+  const Schedule S = make_schedule(*prob);
+  out->ckpt_states = L.nckpt;
+  out->schedule_advances = S.advances;
+  out->adjoint_forward_steps = S.adjoint_steps;
   return FWI_OK;
 }
 
@@ -1346,6 +1506,7 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   for (int r = 0; r < prob->nrec; ++r)
     if (bad_node(rec_node[r])) { delete p; return FWI_ERR_ARG; }
   build_tiles(p);
+  p->sched = make_schedule(*prob);
   p->c_lam = reference_eigen(1.0, 0.0);
   p->c_mu = reference_eigen(0.0, 1.0);
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {

@@ -57,14 +57,14 @@ def depth_profile(prob, field, x=0.0, y=0.0):
     return az, field[np.asarray(ids)]
 
 
-def run(iters=40, pulse="p20", nsteps=450, precision="fp32", device="cuda", log=print):
+def run(iters=40, pulse="p20", nsteps=450, precision="fp32", device="cuda", log=print, grad_full=True):
     t0 = time.perf_counter()
     wl = W.section43(pulse, nsteps)
     obs = refined_data(pulse, nsteps, device)
     log(f"refined-mesh data: {time.perf_counter() - t0:.1f} s")
     prec = B.FWI_FP32 if precision == "fp32" else B.FWI_FP64
     S = Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node, precision=prec, device=device,
-               traction=wl.traction)
+               traction=wl.traction, grad_full=grad_full)
     rho, wav = S.tensor(wl.rho), S.tensor(wl.wavelet)
     lam0, mu0 = S.tensor(wl.lam), S.tensor(wl.mu)
     opts = FwiOptions(reg="tv", tv_eps=0.01e12, max_iter=iters)
@@ -92,7 +92,8 @@ def run(iters=40, pulse="p20", nsteps=450, precision="fp32", device="cuda", log=
                n_state=int(S.sizes.n_state), precision=precision, iterations=len(hist.alpha),
                seconds=secs, solves=hist.solves, adjoints=hist.adjoints,
                J_start=hist.J[0], J_final=hist.J[-1], J_reduction=hist.J[0] / hist.J[-1],
-               J_history=hist.J, lam_err_start=err(wl.lam, lt), mu_err_start=err(wl.mu, mt),
+               grad_full=bool(grad_full), J_history=hist.J, alpha=hist.alpha, backtracks=hist.backtracks,
+               R=hist.R, lam_err_start=err(wl.lam, lt), mu_err_start=err(wl.mu, mt),
                lam_err=err(la, lt), mu_err=err(ma, mt),
                profile_00={"z": z.tolist(), "lam_MPa": (pl / 1e6).tolist(), "mu_MPa": (pm / 1e6).tolist(),
                            "target_MPa": (pt / 1e6).tolist()})
@@ -104,12 +105,16 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=40)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--restricted-gradient", action="store_true",
+                    help="gradient from the interior bricks only (Sec. 3.1.3) instead of the full chain rule")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("the inversion runs on the GPU")
-    out = run(args.iters, precision=args.precision, log=lambda m: print(m, flush=True))
-    print(json.dumps({k: v for k, v in out.items() if k not in ("J_history", "profile_00")}), flush=True)
+    out = run(args.iters, precision=args.precision, log=lambda m: print(m, flush=True),
+              grad_full=not args.restricted_gradient)
+    print(json.dumps({k: v for k, v in out.items()
+                      if k not in ("J_history", "profile_00", "alpha", "backtracks", "R")}), flush=True)
     if args.json:
         with open(args.json, "w") as f:
             json.dump(out, f, indent=1)

@@ -37,12 +37,14 @@ class Solver:
     """
 
     def __init__(self, prob, src_node, src_dir, rec_node, precision=B.FWI_FP64,
-                 ckpt_every=0, device="cuda", traction=None, grad_full=False):
+                 ckpt_every=0, device="cuda", traction=None, grad_full=False, ckpt_slots=0):
         """traction: None (point loads src_node / src_dir), or (xmin, xmax,
         ymin, ymax, direction) of a uniform surface traction applied by every
         source; the wavelet is then the traction in Pa.  ckpt_every = -1 makes
         a forward-only plan.  grad_full: the gradient includes the PML terms
-        of the material carried outward from the interface."""
+        of the material carried outward from the interface.  ckpt_slots: with
+        ckpt_every = k > 0, at most that many stored states and binomial
+        checkpointing over the k-step segments (0: a state per segment)."""
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (HIP device); no CPU fallback exists")
         self.device = torch.device(device)
@@ -50,7 +52,7 @@ class Solver:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
         self.nsrc = int(len(src_node))
         self.nrec = int(len(rec_node))
-        self.problem = B.make_problem(prob, self.nsrc, self.nrec, precision, ckpt_every, grad_full)
+        self.problem = B.make_problem(prob, self.nsrc, self.nrec, precision, ckpt_every, grad_full, ckpt_slots)
         self.sizes = B.fwi_query(self.problem)
         self.nsteps = prob.nsteps
         self.plan = B.fwi_plan_create(self.problem, np.asarray(src_node), np.asarray(src_dir),
