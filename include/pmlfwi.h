@@ -289,6 +289,16 @@ fwi_status fwi_check_model(fwi_plan* plan, void* stream, const double* rho,
 fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b,
                    const double* w, double* out);
 
+/* out = alpha x + beta y, device vectors of length n (y may be null when
+ * beta = 0; out may alias x or y): the vector updates of the optimizer --
+ * the L-BFGS two-loop recursion, the model update (19), the biased lambda
+ * direction (25) and the gradient difference y = g_{k+1} - g_k. */
+fwi_status fwi_axpby(void* stream, int64_t n, double alpha, const double* x, double beta,
+                     const double* y, double* out);
+/* out[0] = max_i |x_i| (device; the step-length rule of the first L-BFGS
+ * iteration, max |s| = a fraction of max |m|). */
+fwi_status fwi_absmax(void* stream, int64_t n, const double* x, double* out);
+
 /* ---- Learned warm start: a small 3D convolutional network (FP32, device
  * arrays, NCDHW: batch, channel, then three spatial axes, the last fastest).
  * Cubic kernels of size K = 1 or 3 with zero padding K/2 and per-axis

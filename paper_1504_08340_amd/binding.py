@@ -83,6 +83,8 @@ _lib.fwi_regularization.argtypes = [_P, _P, ctypes.c_int, ctypes.c_double, _P, _
 _lib.fwi_material_mass.argtypes = [_P, _P, _P]
 _lib.fwi_gradient_finalize.argtypes = [_P, _P, _P, _P, ctypes.c_double, _P]
 _lib.fwi_dot.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
+_lib.fwi_axpby.argtypes = [_P, ctypes.c_int64, ctypes.c_double, _P, ctypes.c_double, _P, _P]
+_lib.fwi_absmax.argtypes = [_P, ctypes.c_int64, _P, _P]
 _lib.fwi_check_model.argtypes = [_P, _P, _P, _P, _P, _P]
 
 
@@ -101,14 +103,14 @@ _lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c
 _lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]
 for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_set_loads", "fwi_surface_traction", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
-           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_axpby", "fwi_absmax", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_set_loads", "fwi_surface_traction", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
-           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_check_model",
+           "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_axpby", "fwi_absmax", "fwi_check_model",
            "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes", "fwi_status_string", "fwi_last_error")
 FWI_REG_TIKHONOV, FWI_REG_TV = 0, 1
@@ -279,6 +281,15 @@ def fwi_check_model(plan, stream, rho, lam, mu):
 
 def fwi_dot(stream, n, a, b, w, out):
     _check(_lib.fwi_dot(_stream(stream), int(n), _ptr(a), _ptr(b), _ptr(w), _ptr(out)), None, "fwi_dot")
+
+
+def fwi_axpby(stream, n, alpha, x, beta, y, out):
+    _check(_lib.fwi_axpby(_stream(stream), int(n), float(alpha), _ptr(x), float(beta), _ptr(y), _ptr(out)),
+           None, "fwi_axpby")
+
+
+def fwi_absmax(stream, n, x, out):
+    _check(_lib.fwi_absmax(_stream(stream), int(n), _ptr(x), _ptr(out)), None, "fwi_absmax")
 
 
 def conv_shape(N, Ci, D, H, W, Co, K, strides):

@@ -1866,6 +1866,21 @@ fwi_status fwi_dot(void* stream, int64_t n, const double* a, const double* b, co
   return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
 }
 
+fwi_status fwi_axpby(void* stream, int64_t n, double alpha, const double* x, double beta, const double* y,
+                     double* out) {
+  if (n < 0 || (n > 0 && (!x || !out || (beta != 0.0 && !y)))) return FWI_ERR_ARG;
+  if (n == 0) return FWI_OK;
+  const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 8192);
+  axpby_kernel<<<nb, 256, 0, (hipStream_t)stream>>>((long long)n, alpha, x, beta, y, out);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_absmax(void* stream, int64_t n, const double* x, double* out) {
+  if (n < 0 || !out || (n > 0 && !x)) return FWI_ERR_ARG;
+  absmax_kernel<<<1, 1024, 0, (hipStream_t)stream>>>((long long)n, x, out);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
 static bool conv_shape(const fwi_conv_shape* s, ConvShape& c) {
   if (!s || s->N < 1 || s->Ci < 1 || s->D < 1 || s->H < 1 || s->W < 1 || s->Co < 1) return false;
   if ((s->K != 1 && s->K != 3) || s->sd < 1 || s->sh < 1 || s->sw < 1) return false;

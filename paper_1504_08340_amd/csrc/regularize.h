@@ -176,4 +176,28 @@ __global__ void __launch_bounds__(1024) dot_kernel(long long n, const double* __
   if (threadIdx.x == 0) out[0] = part[0];
 }
 
+// out = alpha x + beta y (y may be null when beta = 0; out may alias x or y):
+// the vector updates of the optimizer (L-BFGS two-loop recursion, the model
+// update (19), the biased direction (25), y = g1 - g).  FP64, elementwise.
+__global__ void axpby_kernel(long long n, double alpha, const double* x, double beta, const double* y,
+                             double* out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = beta == 0.0 ? alpha * x[i] : alpha * x[i] + beta * y[i];
+}
+
+// out[0] = max_i |x_i| (one workgroup; max is exact, so any order gives the same bits).
+__global__ void __launch_bounds__(1024) absmax_kernel(long long n, const double* __restrict__ x,
+                                                      double* __restrict__ out) {
+  __shared__ double part[1024];
+  double m = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(x[i]));
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
+}
+
 }  // namespace pmlfwi

@@ -3,9 +3,10 @@ Algorithm 1 (Armijo backtracking), regularization factor rule (24),
 source-frequency continuation (3.3.2) and the biased lambda direction (25).
 
 Every PDE solve, the regularization terms (8)/(9), M~ (C.1a), the control
-problem (18) and every inner product run in libpmlfwi.so; the vectors live
-in torch tensors on the device and the model updates (19) are torch
-element-wise operations.  FP64 for the model, the gradients, the misfit and
+problem (18), every inner product, the vector updates (fwi_axpby: the L-BFGS
+recursion, the model update (19), the biased direction (25), gradient
+differences) and the max-norms (fwi_absmax) run in libpmlfwi.so; torch
+holds the vectors and concatenates them.  FP64 for the model, the gradients, the misfit and
 the optimizer's inner products; the wavefield precision is the solver's.
 
 Choices the paper leaves open:
@@ -125,22 +126,38 @@ class _Dots:
         return float(self.out[0])
 
 
+def _axpby(alpha, x, beta=0.0, y=None, out=None):
+    """alpha x + beta y on the device (fwi_axpby); a new tensor unless out."""
+    out = torch.empty_like(x) if out is None else out
+    B.fwi_axpby(None, x.numel(), alpha, x, beta, y, out)
+    return out
+
+
+class _AbsMax:
+    def __init__(self, dev):
+        self.out = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def __call__(self, x):
+        B.fwi_absmax(None, x.numel(), x, self.out)
+        return float(self.out[0])
+
+
 def _lbfgs_direction(dot, g, pairs, w):
     if not pairs:
         return None
-    q = g.clone()
+    q = _axpby(1.0, g)
     coef = []
     for s, y in reversed(pairs):
         r = 1.0 / dot(y, s, w)
         a = r * dot(s, q, w)
         coef.append((a, r))
-        q.add_(y, alpha=-a)
+        _axpby(1.0, q, -a, y, out=q)
     s_last, y_last = pairs[-1]
-    q.mul_(dot(s_last, y_last, w) / dot(y_last, y_last, w))
+    _axpby(dot(s_last, y_last, w) / dot(y_last, y_last, w), q, out=q)
     for (s, y), (a, r) in zip(pairs, reversed(coef)):
         b = r * dot(y, q, w)
-        q.add_(s, alpha=a - b)
-    return q.neg_()
+        _axpby(1.0, q, a - b, s, out=q)
+    return _axpby(-1.0, q, out=q)
 
 
 def invert(stages, lam0, mu0, mass, opts: FwiOptions, history: FwiHistory | None = None,
@@ -152,6 +169,7 @@ def invert(stages, lam0, mu0, mass, opts: FwiOptions, history: FwiHistory | None
     h = history or FwiHistory()
     t0 = time.perf_counter()
     dot = _Dots(lam0.device)
+    absmax = _AbsMax(lam0.device)
     n = lam0.numel()
     lam, mu = lam0.clone(), mu0.clone()
     w = torch.cat([mass, mass])
@@ -203,24 +221,27 @@ def invert(stages, lam0, mu0, mass, opts: FwiOptions, history: FwiHistory | None
                 return torch.cat([gl, gmu])
 
             g = representer(gl_mis, gm_mis, gl_reg, gm_reg)
-            gmax = float(g.abs().max())
+            gmax = absmax(g)
             if gmax == 0.0:
                 stop = True
                 break
-            mmax = max(float(lam.abs().max()), float(mu.abs().max()))
+            mmax = max(absmax(lam), absmax(mu))
             s = _lbfgs_direction(dot, g, pairs, w)
             if s is None:
-                s = g * (-opts.first_step * mmax / gmax)
+                s = _axpby(-opts.first_step * mmax / gmax, g)
             if opts.invert_lam and opts.invert_mu and opts.bias_iters > 0:
                 W = max(0.0, 1.0 - it / opts.bias_iters)
                 sl, sm = s[:n], s[n:]
                 nl, nm = dot(sl, sl) ** 0.5, dot(sm, sm) ** 0.5
                 if W > 0 and nl > 0 and nm > 0:
-                    s = torch.cat([nl * (W * sm / nm + (1 - W) * sl / nl), sm])
+                    biased = torch.empty_like(s)
+                    _axpby(W * nl / nm, sm, 1.0 - W, sl, out=biased[:n])     # (25)
+                    biased[n:].copy_(sm)
+                    s = biased
             slope = dot(g, s, w)
             if slope >= 0:
                 pairs = []
-                s = g * (-opts.first_step * mmax / gmax)
+                s = _axpby(-opts.first_step * mmax / gmax, g)
                 slope = dot(g, s, w)
             s_lam, s_mu = s[:n], s[n:]
 
@@ -228,7 +249,7 @@ def invert(stages, lam0, mu0, mass, opts: FwiOptions, history: FwiHistory | None
             accepted = None
             nbt = 0
             for nbt in range(opts.max_backtracks + 1):
-                lt, mt = lam + alpha * s_lam, mu + alpha * s_mu
+                lt, mt = _axpby(1.0, lam, alpha, s_lam), _axpby(1.0, mu, alpha, s_mu)      # (19)
                 Ja = st.forward(lt, mt)
                 if opts.reg is not None:
                     Ja += Rl * st.regularize(lt)[0] + Rm * st.regularize(mt)[0]
@@ -249,8 +270,8 @@ def invert(stages, lam0, mu0, mass, opts: FwiOptions, history: FwiHistory | None
             else:
                 greg_l = greg_m = zeros
             g1 = representer(gl_new, gm_new, greg_l, greg_m)
-            y = g1 - g
-            sk = alpha * s
+            y = _axpby(1.0, g1, -1.0, g)
+            sk = _axpby(alpha, s)
             if dot(sk, y, w) > 0:
                 pairs.append((sk, y))
                 if len(pairs) > opts.memory:

@@ -57,7 +57,7 @@ def depth_profile(prob, field, x=0.0, y=0.0):
     return az, field[np.asarray(ids)]
 
 
-def run(iters=40, pulse="p20", nsteps=450, precision="fp32", device="cuda", log=print, grad_full=True):
+def run(iters=40, pulse="p20", nsteps=450, precision="fp32", device="cuda", log=print, grad_full=False):
     t0 = time.perf_counter()
     wl = W.section43(pulse, nsteps)
     obs = refined_data(pulse, nsteps, device)
@@ -105,14 +105,15 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--iters", type=int, default=40)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
-    ap.add_argument("--restricted-gradient", action="store_true",
-                    help="gradient from the interior bricks only (Sec. 3.1.3) instead of the full chain rule")
+    ap.add_argument("--full-gradient", action="store_true",
+                    help="chain rule through the material carried into the PML instead of the gradient "
+                         "restricted to the interior bricks (Sec. 3.1.3)")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("the inversion runs on the GPU")
     out = run(args.iters, precision=args.precision, log=lambda m: print(m, flush=True),
-              grad_full=not args.restricted_gradient)
+              grad_full=args.full_gradient)
     print(json.dumps({k: v for k, v in out.items()
                       if k not in ("J_history", "profile_00", "alpha", "backtracks", "R")}), flush=True)
     if args.json:

@@ -84,3 +84,23 @@ def test_regularization_argument_errors(P):
     with pytest.raises(P.FwiError, match="kind"):
         P.fwi_regularization(S.plan, None, 5, 1.0, f, None, g)
     S.close()
+
+
+def test_optimizer_vector_kernels():
+    """fwi_axpby (in place and out of place) and fwi_absmax against numpy."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1504_08340_amd as P
+    rng = np.random.default_rng(4)
+    n = 100_003
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    tx, ty = (torch.tensor(a, device="cuda") for a in (x, y))
+    out = torch.empty_like(tx)
+    P.binding.fwi_axpby(None, n, 0.7, tx, -1.3, ty, out)
+    np.testing.assert_allclose(out.cpu().numpy(), 0.7 * x - 1.3 * y, rtol=1e-15, atol=1e-15)
+    P.binding.fwi_axpby(None, n, 2.5, tx, 0.0, None, tx)
+    np.testing.assert_allclose(tx.cpu().numpy(), 2.5 * x, rtol=1e-15)
+    m = torch.empty(1, dtype=torch.float64, device="cuda")
+    P.binding.fwi_absmax(None, n, ty, m)
+    assert m.item() == np.abs(y).max()
