@@ -319,6 +319,16 @@ fwi_status fwi_conv3d_forward(void* stream, const fwi_conv_shape* shape, const f
 fwi_status fwi_conv3d_backward(void* stream, const fwi_conv_shape* shape, const float* x,
                                const float* w, const float* y, const float* dy, int relu,
                                float* dx, float* dw, float* db);
+/* BF16 inference (the network's forward pass on the matrix cores):
+ * fwi_to_bf16 rounds FP32 to BF16 (nearest, ties to even; bit patterns in
+ * uint16).  fwi_conv3d_forward_bf16: y = act(b + w * x) with x [N][Ci][D][H][W]
+ * and w [Co][Ci][K][K][K] in BF16, as an implicit GEMM on BF16 MFMA with FP32
+ * accumulation; bias (FP32) and ReLU in FP32; y is BF16 (out_fp32 = 0, hidden
+ * layers) or FP32 (out_fp32 = 1, the head).  Same shapes as
+ * fwi_conv3d_forward; N <= 65535. */
+fwi_status fwi_to_bf16(void* stream, int64_t n, const float* in, uint16_t* out);
+fwi_status fwi_conv3d_forward_bf16(void* stream, const fwi_conv_shape* shape, const uint16_t* x,
+                                   const uint16_t* w, const float* b, int relu, int out_fp32, void* y);
 /* loss[0] = 1/(2n) sum (y - t)^2, grad = (y - t)/n; either may be null. */
 fwi_status fwi_mse(void* stream, int64_t n, const float* y, const float* t, float* loss,
                    float* grad);

@@ -107,3 +107,22 @@ def grid_to_nodes(c, NIX, NIY, NIZ, base):
     Wx, Wy, Wz = weights(NIX, gx), weights(NIY, gy), weights(NIZ, gz, reverse=True)
     field = np.einsum("zZ,yY,xX,ZYX->zyx", Wz, Wy, Wx, c)     # node grid [NIZ][NIY][NIX]
     return base * (1.0 + field.ravel())
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value, ties to even (the 16 high bits of the
+    FP32 pattern after adding 0x7FFF plus the lowest kept bit); finite input."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(x, weights, biases, strides, relus):
+    """The network's forward pass as BF16 inference defines it: input,
+    weights and hidden activations rounded to BF16, sums in FP64 here (FP32 on
+    the device), bias and ReLU before the rounding; the last output unrounded."""
+    a = bf16_round(x)
+    for li, (w, b, s, r) in enumerate(zip(weights, biases, strides, relus)):
+        y = conv3d_forward(a, bf16_round(w), None if b is None else np.asarray(b, np.float64), s, r)
+        a = y if li == len(weights) - 1 else bf16_round(y.astype(np.float32))
+    return a

@@ -97,6 +97,8 @@ _F = ctypes.c_float
 _lib.fwi_conv3d_forward.argtypes = [_P, _CS, _P, _P, _P, ctypes.c_int, _P]
 _lib.fwi_conv3d_backward.argtypes = [_P, _CS, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P]
 _lib.fwi_mse.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
+_lib.fwi_to_bf16.argtypes = [_P, ctypes.c_int64, _P, _P]
+_lib.fwi_conv3d_forward_bf16.argtypes = [_P, _CS, _P, _P, _P, ctypes.c_int, ctypes.c_int, _P]
 _lib.fwi_adam.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P, _F, _F, _F, _F, ctypes.c_int]
 _lib.fwi_trace_features.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _F, _P]
@@ -104,14 +106,14 @@ _lib.fwi_grid_to_nodes.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctype
 for _f in ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_set_loads", "fwi_surface_traction", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_axpby", "fwi_absmax", "fwi_check_model",
-           "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
+           "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_to_bf16", "fwi_conv3d_forward_bf16", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("fwi_query", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_set_loads", "fwi_surface_traction", "fwi_forward", "fwi_forward_noalloc", "fwi_misfit",
            "fwi_adjoint_gradient", "fwi_adjoint_gradient_appb", "fwi_apply_operator", "fwi_timing_enable", "fwi_timing_read",
            "fwi_regularization", "fwi_material_mass", "fwi_gradient_finalize", "fwi_dot", "fwi_axpby", "fwi_absmax", "fwi_check_model",
-           "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_mse", "fwi_adam", "fwi_trace_features",
+           "fwi_conv3d_forward", "fwi_conv3d_backward", "fwi_to_bf16", "fwi_conv3d_forward_bf16", "fwi_mse", "fwi_adam", "fwi_trace_features",
            "fwi_grid_to_nodes", "fwi_status_string", "fwi_last_error")
 FWI_REG_TIKHONOV, FWI_REG_TV = 0, 1
 KERNEL_CLASSES = ("interior", "pml", "nodal", "interior_adj", "pml_adj")
@@ -307,6 +309,15 @@ def fwi_conv3d_forward(stream, shape, x, w, b, relu, y):
 def fwi_conv3d_backward(stream, shape, x, w, y, dy, relu, dx, dw, db):
     _check(_lib.fwi_conv3d_backward(_stream(stream), ctypes.byref(shape), _ptr(x), _ptr(w), _ptr(y), _ptr(dy),
                                     int(relu), _ptr(dx), _ptr(dw), _ptr(db)), None, "fwi_conv3d_backward")
+
+
+def fwi_to_bf16(stream, n, x, out):
+    _check(_lib.fwi_to_bf16(_stream(stream), int(n), _ptr(x), _ptr(out)), None, "fwi_to_bf16")
+
+
+def fwi_conv3d_forward_bf16(stream, shape, x, w, b, relu, out_fp32, y):
+    _check(_lib.fwi_conv3d_forward_bf16(_stream(stream), ctypes.byref(shape), _ptr(x), _ptr(w), _ptr(b), int(relu),
+                                        int(out_fp32), _ptr(y)), None, "fwi_conv3d_forward_bf16")
 
 
 def fwi_mse(stream, n, y, t, loss, grad):

@@ -8,6 +8,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "mfma.h"
+
 namespace pmlfwi {
 
 struct ConvShape {
@@ -53,6 +55,72 @@ __global__ void __launch_bounds__(256) conv3d_forward_kernel(ConvShape c, const 
     }
   }
   y[o] = (relu && acc < 0.0f) ? 0.0f : acc;
+}
+
+// ---- BF16 inference on the matrix cores -----------------------------------
+// The convolution as an implicit GEMM: C[co][p] = sum_k W[co][k] X[k][p] with
+// k = (ci, kd, kh, kw) and p the output position of one batch entry; W is
+// the BF16 weight tensor read as a [Co][Ci K^3] matrix, X the zero-padded
+// input patch gathered on the fly (im2col without a buffer).  One wave per 16
+// output positions and every 16-row tile of output channels, v_mfma 16x16x16
+// BF16 with FP32 accumulation; bias and ReLU in FP32, output rounded to BF16
+// (hidden layers) or kept FP32 (the head).
+__global__ void to_bf16_kernel(long long n, const float* __restrict__ in, unsigned short* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = bf16_bits(in[i]);
+}
+
+constexpr int CONV_MFMA_THREADS = 256;   // 4 waves, 64 output positions per workgroup
+
+__global__ void __launch_bounds__(CONV_MFMA_THREADS)
+conv3d_bf16_mfma_kernel(ConvShape c, const unsigned short* __restrict__ x, const unsigned short* __restrict__ w,
+                        const float* __restrict__ b, int relu, int out_fp32, void* __restrict__ y) {
+  const int P = c.Do * c.Ho * c.Wo;
+  const int KK = c.K * c.K * c.K, Kdim = c.Ci * KK, pad = c.K / 2;
+  const int n = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int col0 = blockIdx.x * 64 + wave * 16;
+  const int p = col0 + i;                        // this lane's output position (B column)
+  const bool pin = p < P;
+  const int ow = pin ? p % c.Wo : 0, oh = pin ? (p / c.Wo) % c.Ho : 0, od = pin ? p / (c.Wo * c.Ho) : 0;
+  const unsigned short* xn = x + (size_t)n * c.Ci * c.D * c.H * c.W;
+  const int nrt = (c.Co + 15) / 16;
+  for (int rt = 0; rt < nrt; ++rt) {
+    const int row = rt * 16 + i;                 // this lane's A row (output channel)
+    v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < Kdim; k0 += 16) {
+      v4s a, bb;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 4 * g + j;
+        a[j] = (row < c.Co && k < Kdim) ? (short)w[(size_t)row * Kdim + k] : (short)0;
+        short v = 0;
+        if (pin && k < Kdim) {
+          const int ci = k / KK, r = k - ci * KK;
+          const int kd = r / (c.K * c.K), kh = (r / c.K) % c.K, kw = r % c.K;
+          const int id = od * c.sd + kd - pad, ih = oh * c.sh + kh - pad, iw = ow * c.sw + kw - pad;
+          if (id >= 0 && id < c.D && ih >= 0 && ih < c.H && iw >= 0 && iw < c.W)
+            v = (short)xn[(((size_t)ci * c.D + id) * c.H + ih) * c.W + iw];
+        }
+        bb[j] = v;
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
+    }
+    // lane holds C[rt*16 + 4 g + r][col0 + i], r = 0..3
+    if (pin) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = rt * 16 + 4 * g + r;
+        if (co >= c.Co) continue;
+        float v = acc[r] + (b ? b[co] : 0.0f);
+        if (relu && v < 0.0f) v = 0.0f;
+        const size_t o = ((size_t)n * c.Co + co) * P + p;
+        if (out_fp32) ((float*)y)[o] = v;
+        else ((unsigned short*)y)[o] = bf16_bits(v);
+      }
+    }
+  }
 }
 
 // g = dL/d(pre-activation) from dL/dy and, with ReLU, the activated output y.

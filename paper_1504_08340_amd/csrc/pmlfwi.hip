@@ -181,6 +181,9 @@ struct fwi_plan {
   // (fork and join through events on the caller's stream)
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // third stream: the second PML part beside the first (PMLFWI_CONCURRENT 2)
+  hipStream_t side2 = nullptr;
+  hipEvent_t join2_ev = nullptr;
   // largest eigenvalues of M^{-1} K for the unit reference brick with lam = 1,
   // mu = 0 and lam = 0, mu = 1 (stability bound of fwi_check_model)
   double c_lam = 0.0, c_mu = 0.0;
@@ -990,12 +993,12 @@ struct Run {
   // two launches may run at the same time: the interior one goes to the plan's
   // second stream when both lists are non-empty.
   template <int PART>
-  void launch_pml(bool adj, dim3 grid, int nt, const R* Y, long long reg) {
+  void launch_pml(bool adj, dim3 grid, int nt, const R* Y, long long reg, hipStream_t sp) {
     if (adj)
-      pml_element_kernel<R, TX, TY, TZ, true, SRCLOOP, PART><<<grid, ETHREADS, 0, st>>>(
+      pml_element_kernel<R, TX, TY, TZ, true, SRCLOOP, PART><<<grid, ETHREADS, 0, sp>>>(
           g(), p->d_tiles_pml, nt, p->nsrc, Y, reg, lam(), mu(), res(), L.part);
     else
-      pml_element_kernel<R, TX, TY, TZ, false, SRCLOOP, PART><<<grid, ETHREADS, 0, st>>>(
+      pml_element_kernel<R, TX, TY, TZ, false, SRCLOOP, PART><<<grid, ETHREADS, 0, sp>>>(
           g(), p->d_tiles_pml, nt, p->nsrc, Y, reg, lam(), mu(), res(), L.part);
   }
 
@@ -1007,9 +1010,11 @@ struct Run {
     hipStream_t si = st;
     const bool pml = !interior_only && !p->tiles_pml.empty();
     const bool fork = PMLFWI_CONCURRENT && !p->tiles_int.empty() && pml;
+    const bool fork2 = fork && PMLFWI_CONCURRENT == 2 && PMLFWI_PML_SPLIT;
     if (fork) {
       HIP_TRY(p, hipEventRecord(p->fork_ev, st));
       HIP_TRY(p, hipStreamWaitEvent(p->side, p->fork_ev, 0));
+      if (fork2) HIP_TRY(p, hipStreamWaitEvent(p->side2, p->fork_ev, 0));
       si = p->side;
     }
     if (!p->tiles_int.empty()) {
@@ -1029,10 +1034,13 @@ struct Run {
       const dim3 grid(8u * (unsigned)((nt + 7) / 8), SRCLOOP ? 1 : ns);
       TimedLaunch tl(p, adj ? FWI_K_PML_ADJ : FWI_K_PML, st);
       if (PMLFWI_PML_SPLIT) {
-        launch_pml<PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg);
-        launch_pml<PML_ALL ^ PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg);
+        // the two row types write disjoint rows: with three streams the
+        // second part runs beside the first and the interior bricks
+        launch_pml<PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg, st);
+        launch_pml<PML_ALL ^ PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg, fork2 ? p->side2 : st);
+        if (fork2) HIP_TRY(p, hipEventRecord(p->join2_ev, p->side2));
       } else {
-        launch_pml<PML_ALL>(adj, grid, nt, Y, reg);
+        launch_pml<PML_ALL>(adj, grid, nt, Y, reg, st);
       }
     }
     if (pml && pfwd) {
@@ -1043,6 +1051,7 @@ struct Run {
           G, p->d_tiles_pml, nt, ns, Y, reg, pfwd, (long long)(9LL * G.sp), gw, gacc(), L.gpart);
     }
     if (fork) HIP_TRY(p, hipStreamWaitEvent(st, p->join_ev, 0));
+    if (fork2) HIP_TRY(p, hipStreamWaitEvent(st, p->join2_ev, 0));
     HIP_TRY(p, hipGetLastError());
     return FWI_OK;
   }
@@ -1544,6 +1553,10 @@ fwi_status fwi_plan_create(const fwi_problem* prob, const int32_t* src_node, con
   }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
+  if (e == hipSuccess && PMLFWI_CONCURRENT == 2) {
+    e = hipStreamCreateWithFlags(&p->side2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join2_ev, hipEventDisableTiming);
+  }
   if (e == hipSuccess) {
     what = "pinned model-check result";
     e = hipHostMalloc((void**)&p->h_info, 8 * sizeof(double), hipHostMallocDefault);
@@ -1692,6 +1705,9 @@ fwi_status fwi_plan_destroy(fwi_plan* p) {
   if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   if (p->join_ev) (void)hipEventDestroy(p->join_ev);
   if (p->side) (void)hipStreamDestroy(p->side);
+  if (p->side2) (void)hipStreamSynchronize(p->side2);
+  if (p->join2_ev) (void)hipEventDestroy(p->join2_ev);
+  if (p->side2) (void)hipStreamDestroy(p->side2);
   (void)hipFree(p->d_tiles_int);
   (void)hipFree(p->d_tiles_pml);
   (void)hipFree(p->d_src);
@@ -1895,6 +1911,26 @@ fwi_status fwi_conv3d_forward(void* stream, const fwi_conv_shape* shape, const f
   if (!conv_shape(shape, c) || !x || !w || !y) return FWI_ERR_ARG;
   const long long n = (long long)c.N * c.Co * c.Do * c.Ho * c.Wo;
   conv3d_forward_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(c, x, w, b, relu, y);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_to_bf16(void* stream, int64_t n, const float* in, uint16_t* out) {
+  if (n < 0 || (n > 0 && (!in || !out))) return FWI_ERR_ARG;
+  if (n == 0) return FWI_OK;
+  const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 8192);
+  to_bf16_kernel<<<nb, 256, 0, (hipStream_t)stream>>>((long long)n, in, (unsigned short*)out);
+  return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
+}
+
+fwi_status fwi_conv3d_forward_bf16(void* stream, const fwi_conv_shape* shape, const uint16_t* x, const uint16_t* w,
+                                   const float* b, int relu, int out_fp32, void* y) {
+  ConvShape c;
+  if (!conv_shape(shape, c) || !x || !w || !y) return FWI_ERR_ARG;
+  const long long P = (long long)c.Do * c.Ho * c.Wo;
+  if (c.N > 65535) return FWI_ERR_ARG;
+  const dim3 grid((unsigned)((P + 63) / 64), (unsigned)c.N);
+  conv3d_bf16_mfma_kernel<<<grid, CONV_MFMA_THREADS, 0, (hipStream_t)stream>>>(
+      c, (const unsigned short*)x, (const unsigned short*)w, b, relu, out_fp32, y);
   return hipGetLastError() == hipSuccess ? FWI_OK : FWI_ERR_HIP;
 }
 

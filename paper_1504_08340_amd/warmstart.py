@@ -5,7 +5,8 @@ channels and a 1x1x1 head) maps the vertical displacement traces of the nine
 surface loads of the layered 32x32x16 m workload (32 x 32 receivers at 1 m
 spacing, 256 time samples) to relative perturbations of lam and mu about
 the linear vs trend on a 16 x 16 x 8 grid of 2 m cells; the start model is
-the trend times (1 + interpolated perturbation).  Training data are seeded
+the trend times (1 + interpolated perturbation).  Training runs in FP32,
+inference in BF16 on the matrix cores (FP32 accumulation).  Training data are seeded
 random layered profiles whose traces the forward solver of this library
 computes; training, inference and every layer's forward and backward pass
 run in the library's HIP kernels (fwi_conv3d_*, fwi_mse, fwi_adam), with
@@ -82,6 +83,29 @@ class Net:
             acts.append(y)
         return acts
 
+    def forward_bf16(self, x):
+        """Network output for input x (FP32) by BF16 inference on the matrix
+        cores: input, weights and hidden activations rounded to BF16, FP32
+        accumulation, bias and ReLU; the head's output in FP32."""
+        if getattr(self, "_wbf", None) is None or self._wbf_step != self.step:
+            self._wbf = []
+            for w in self.w:
+                t = torch.empty(w.shape, dtype=torch.bfloat16, device=self.dev)
+                B.fwi_to_bf16(None, w.numel(), w, t)
+                self._wbf.append(t)
+            self._wbf_step = self.step
+        n = x.shape[0]
+        a = torch.empty(x.shape, dtype=torch.bfloat16, device=self.dev)
+        B.fwi_to_bf16(None, x.numel(), x.contiguous(), a)
+        last = len(LAYERS) - 1
+        for li, ((ci, co, k, s, relu), sh, w, b) in enumerate(zip(LAYERS, self.shapes(n), self._wbf, self.b)):
+            d, h, ww = _out(sh.D, k, s[0]), _out(sh.H, k, s[1]), _out(sh.W, k, s[2])
+            y = torch.empty((n, co, d, h, ww), dtype=torch.float32 if li == last else torch.bfloat16,
+                            device=self.dev)
+            B.fwi_conv3d_forward_bf16(None, sh, a, w, b, relu, li == last, y)
+            a = y
+        return a
+
     def backward(self, acts, dy):
         """Parameter gradients (w then b, layer order) for dL/d(output) = dy."""
         n = acts[0].shape[0]
@@ -155,11 +179,12 @@ class Probe:
         out = np.stack([lam_t[idx] / self.wl.lam[idx] - 1.0, mu_t[idx] / self.wl.mu[idx] - 1.0])
         return out.astype(np.float32)
 
-    def start_model(self, net, traces):
-        """(lam, mu) from the network for one set of traces."""
+    def start_model(self, net, traces, precision="bf16"):
+        """(lam, mu) from the network for one set of traces; inference in BF16
+        on the matrix cores (precision "bf16") or in FP32 ("fp32")."""
         x = torch.empty((1,) + IN_SHAPE, dtype=torch.float32, device=self.S.device)
         self.features(traces, net.scale, x[0])
-        c = net.forward(x)[-1][0]
+        c = (net.forward_bf16(x) if precision == "bf16" else net.forward(x)[-1])[0]
         lam = torch.empty_like(self.lam0)
         mu = torch.empty_like(self.mu0)
         B.fwi_grid_to_nodes(self.S.plan, None, c[0].contiguous(), 16, 16, 8, self.lam0, lam)

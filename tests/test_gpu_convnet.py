@@ -92,3 +92,67 @@ def test_mse_adam_features_interpolation(P):
     B.fwi_grid_to_nodes(S.plan, None, torch.tensor(c, device=dev), 5, 4, 3, torch.tensor(base, device=dev), o)
     _close(o.cpu().numpy(), C.grid_to_nodes(c.astype(np.float64), nix, niy, niz, base), 1e-6)
     S.close()
+
+
+@pytest.mark.parametrize("xs,co,K,strides,relu", [
+    ((2, 9, 32, 8, 8), 32, 3, (4, 2, 2), True),    # first stage, reduced extents, two channel tiles
+    ((3, 8, 9, 5, 6), 8, 3, (2, 1, 1), True),      # ragged
+    ((2, 32, 5, 4, 4), 2, 1, (1, 1, 1), False),    # head
+    ((1, 3, 7, 7, 7), 20, 3, (1, 1, 1), False),    # channel count not a multiple of 16
+])
+def test_conv_bf16_matrix_cores(P, xs, co, K, strides, relu):
+    """BF16 inference convolution (implicit GEMM on the matrix cores) against
+    the oracle's convolution of the BF16-rounded operands: FP32 output within
+    1e-5 of the largest magnitude (accumulation order only), BF16 output within
+    one BF16 unit of the oracle's rounded value."""
+    import torch
+    from paper_1504_08340_amd import binding as B
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(xs).astype(np.float32)
+    w = (rng.standard_normal((co, xs[1], K, K, K)) * 0.3).astype(np.float32)
+    b = rng.standard_normal(co).astype(np.float32)
+    ref = C.conv3d_forward(C.bf16_round(x), C.bf16_round(w), b.astype(np.float64), strides, relu)
+    dev = torch.device("cuda")
+    X, Wt, Bt = (torch.tensor(a, device=dev) for a in (x, w, b))
+    Xb = torch.empty(X.shape, dtype=torch.bfloat16, device=dev)
+    Wb = torch.empty(Wt.shape, dtype=torch.bfloat16, device=dev)
+    B.fwi_to_bf16(None, X.numel(), X, Xb)
+    B.fwi_to_bf16(None, Wt.numel(), Wt, Wb)
+    assert np.array_equal(Xb.float().cpu().numpy(), C.bf16_round(x).astype(np.float32))
+    sh = B.conv_shape(*xs, co, K, strides)
+    Y32 = torch.empty(ref.shape, dtype=torch.float32, device=dev)
+    B.fwi_conv3d_forward_bf16(None, sh, Xb, Wb, Bt, relu, 1, Y32)
+    Y16 = torch.empty(ref.shape, dtype=torch.bfloat16, device=dev)
+    B.fwi_conv3d_forward_bf16(None, sh, Xb, Wb, Bt, relu, 0, Y16)
+    torch.cuda.synchronize()
+    _close(Y32.cpu().numpy(), ref)
+    got16 = Y16.float().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got16 - C.bf16_round(ref.astype(np.float32))) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
+
+
+def test_network_bf16_inference_vs_oracle():
+    """The shipped network's BF16 forward pass on solver features against
+    the oracle's BF16 inference (rounded operands and activations, FP64 sums):
+    within 1e-2 relative L2 (hidden activations may round the other way where
+    the FP32 and FP64 sums straddle a BF16 boundary); and within 5e-2 of the
+    FP32 forward pass, the accuracy BF16 inference gives up."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import os
+    from paper_1504_08340_amd import warmstart as WS
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    probe = WS.Probe()
+    net = WS.Net.load(os.path.join(root, "paper_1504_08340_amd", "warmstart_weights.npz"), probe.S.device)
+    wl = probe.W.with_model(probe.wl, probe.W.layered_profile_vs(probe.wl.prob, 20_003))
+    tr = probe.traces(probe.S.tensor(wl.lam_true), probe.S.tensor(wl.mu_true))
+    x = torch.empty((1,) + WS.IN_SHAPE, dtype=torch.float32, device=probe.S.device)
+    probe.features(tr, net.scale, x[0])
+    y16 = net.forward_bf16(x).cpu().numpy().astype(np.float64)
+    y32 = net.forward(x)[-1].cpu().numpy().astype(np.float64)
+    ref = C.forward_bf16(x.cpu().numpy(), [w.cpu().numpy() for w in net.w], [b.cpu().numpy() for b in net.b],
+                         [l[3] for l in WS.LAYERS], [l[4] for l in WS.LAYERS])
+    e_ref = np.linalg.norm(y16 - ref) / np.linalg.norm(ref)
+    e_32 = np.linalg.norm(y16 - y32) / np.linalg.norm(y32)
+    print(f"BF16 inference: vs oracle BF16 {e_ref:.2e}, vs FP32 forward {e_32:.2e}")
+    assert e_ref <= 1e-2 and e_32 <= 5e-2

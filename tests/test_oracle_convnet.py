@@ -74,3 +74,20 @@ def test_trace_features_pick_component_receiver_and_step():
     f = C.trace_features(tr, np.array([4, 1]), 4, 1, 3, 2, 2.0)
     assert f[1, 2, 0] == 2.0 * tr[1, 7, 4, 2] and f[0, 3, 1] == 2.0 * tr[0, 10, 1, 2]
     assert C.trace_features(tr, np.array([0]), 5, 1, 3, 0, 1.0)[0, 4, 0] == 0.0
+
+
+def test_bf16_rounding_matches_the_format():
+    """Nearest-even rounding to 8 significant bits: exact BF16 values stay,
+    halfway cases go to the even neighbour, the relative error is at most 2^-8."""
+    from oracle.convnet import bf16_round
+    assert bf16_round(np.float32(1.0)) == 1.0
+    one_ulp = 2.0 ** -7                       # BF16 spacing at 1
+    assert bf16_round(np.float32(1.0 + one_ulp / 2)) == 1.0            # tie -> even (1.0)
+    assert bf16_round(np.float32(1.0 + 3 * one_ulp / 2)) == 1.0 + 2 * one_ulp   # tie -> even
+    assert bf16_round(np.float32(1.0 + 0.6 * one_ulp)) == 1.0 + one_ulp
+    x = np.random.default_rng(2).standard_normal(10000).astype(np.float32)
+    r = bf16_round(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x))
+    # rounded values have at most 8 significant bits
+    m, _ = np.frexp(r)
+    assert np.all(np.abs(m * 2 ** 8 - np.round(m * 2 ** 8)) == 0)
