@@ -57,6 +57,23 @@ __device__ __forceinline__ float dlgl(int q, int a) {
 }
 __device__ __forceinline__ double wlgl(int a) { return a == 1 ? 4.0 / 3.0 : 1.0 / 3.0; }
 
+// The same derivatives in closed form, for the hot loops: with the LGL nodes
+// xi = -1, 0, 1, the basis functions l_0 = xi (xi - 1) / 2, l_1 = 1 - xi^2,
+// l_2 = xi (xi + 1) / 2 have l_p' (xi) = (3 (p - 1)^2 - 2) xi + (p - 1) / 2.
+// dbasis(x, a) = l_a'(x) for a known at compile time (unrolled loops), x the
+// point's coordinate xi_q = q - 1 (exact in any precision); dbasis_coef gives
+// the two factors for a basis index known only at run time.
+template <typename R>
+__device__ __forceinline__ R dbasis(R x, int a) {
+  return a == 0 ? x - R(0.5) : (a == 1 ? R(-2) * x : x + R(0.5));
+}
+template <typename R>
+__device__ __forceinline__ void dbasis_coef(int p, R& c1, R& c0) {
+  const int m = p - 1;
+  c1 = R(3 * m * m - 2);
+  c0 = R(0.5) * R(m);
+}
+
 struct Tile {  // bricks [x, x+cx) x [y, y+cy) x [z, z+cz)
   int x, y, z, c;  // c = cx | cy << 8 | cz << 16
 };
@@ -187,6 +204,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
   const int cx = t.c & 255, cy = (t.c >> 8) & 255, cz = (t.c >> 16) & 255;
   const size_t nn = (size_t)g.sn;
   const R s2h = R(2.0 / g.h);
+  const double wh3 = 0.125 * g.h * g.h * g.h;
 
   // this thread's box node and its constants, shared by the sources
   const int n = threadIdx.x;
@@ -228,12 +246,13 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
       const int px = 2 * ea + qa, py = 2 * eb + qb, pz = 2 * ec + qc;   // box node of the point
       const int nq = px + BX * (py + BY * pz);
       R G[3][3], Gf[3][3];
+      const R xa = R(qa - 1), xb = R(qb - 1), xc = R(qc - 1);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         R gx = 0, gy = 0, gz = 0, fx = 0, fy = 0, fz = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const R cxa = R(dlgl(qa, a)), cya = R(dlgl(qb, a)), cza = R(dlgl(qc, a));
+          const R cxa = dbasis(xa, a), cya = dbasis(xb, a), cza = dbasis(xc, a);
           const int nx = (2 * ea + a) + BX * (py + BY * pz);
           const int ny = px + BX * ((2 * eb + a) + BY * pz);
           const int nz = px + BX * (py + BY * (2 * ec + a));
@@ -249,7 +268,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
         G[d][0] = gx * s2h; G[d][1] = gy * s2h; G[d][2] = gz * s2h;
         if constexpr (GRAD) { Gf[d][0] = fx * s2h; Gf[d][1] = fy * s2h; Gf[d][2] = fz * s2h; }
       }
-      const R wq = R(0.125 * g.h * g.h * g.h * wlgl(qa) * wlgl(qb) * wlgl(qc));
+      const R wq = R(wh3 * wlgl(qa) * wlgl(qb) * wlgl(qc));
       const R la = sLam[nq], m = sMu[nq];
       const R tr = G[0][0] + G[1][1] + G[2][2];
       sS[0][q] = wq * (la * tr + 2 * m * G[0][0]);
@@ -277,10 +296,15 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
     for (int q = threadIdx.x; q < NP; q += blockDim.x) {
       const int pt = q % 27, e0 = q - pt;
       const int pa = pt % 3, pb = (pt / 3) % 3, pc = pt / 9;
+      R ax1, ax0, ay1, ay0, az1, az0;
+      dbasis_coef<R>(pa, ax1, ax0);
+      dbasis_coef<R>(pb, ay1, ay0);
+      dbasis_coef<R>(pc, az1, az0);
       R r0 = 0, r1 = 0, r2 = 0;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const R cxa = R(dlgl(a, pa)), cya = R(dlgl(a, pb)), cza = R(dlgl(a, pc));
+        // derivative of the node's basis function at point a: c1 xi_a + c0
+        const R cxa = ax0 + R(a - 1) * ax1, cya = ay0 + R(a - 1) * ay1, cza = az0 + R(a - 1) * az1;
         const int qx = e0 + a + 3 * pb + 9 * pc;
         const int qy = e0 + pa + 3 * a + 9 * pc;
         const int qz = e0 + pa + 3 * pb + 9 * a;
@@ -441,14 +465,15 @@ __device__ __forceinline__ bool pml_point_value(const Geo& g, int cx, int cy, in
   const int qa = pt % 3, qb = (pt / 3) % 3, qc = pt / 9;
   const int lx = 2 * ea + qa, ly = 2 * eb + qb, lz = 2 * ec + qc;
   R H[3][3];
+  const R xa = R(qa - 1), xb = R(qb - 1), xc = R(qc - 1);
 #pragma unroll
   for (int ii = 0; ii < 3; ++ii) {
     R hx = 0, hy = 0, hz = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      hx += R(dlgl(qa, a)) * sW[(0 + ii) * NB + (2 * ea + a) + BX * (ly + BY * lz)];
-      hy += R(dlgl(qb, a)) * sW[(3 + ii) * NB + lx + BX * ((2 * eb + a) + BY * lz)];
-      hz += R(dlgl(qc, a)) * sW[(6 + ii) * NB + lx + BX * (ly + BY * (2 * ec + a))];
+      hx += dbasis(xa, a) * sW[(0 + ii) * NB + (2 * ea + a) + BX * (ly + BY * lz)];
+      hy += dbasis(xb, a) * sW[(3 + ii) * NB + lx + BX * ((2 * eb + a) + BY * lz)];
+      hz += dbasis(xc, a) * sW[(6 + ii) * NB + lx + BX * (ly + BY * (2 * ec + a))];
     }
     H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
   }
@@ -731,14 +756,15 @@ pml_gradient_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
       const int px = 2 * ea + qa, py = 2 * eb + qb, pz = 2 * ec + qc;
       const int nq = px + BX * (py + BY * pz);
       R H[3][3];
+      const R xa = R(qa - 1), xb = R(qb - 1), xc = R(qc - 1);
 #pragma unroll
       for (int ii = 0; ii < 3; ++ii) {
         R hx = 0, hy = 0, hz = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          hx += R(dlgl(qa, a)) * sW[0 + ii][(2 * ea + a) + BX * (py + BY * pz)];
-          hy += R(dlgl(qb, a)) * sW[3 + ii][px + BX * ((2 * eb + a) + BY * pz)];
-          hz += R(dlgl(qc, a)) * sW[6 + ii][px + BX * (py + BY * (2 * ec + a))];
+          hx += dbasis(xa, a) * sW[0 + ii][(2 * ea + a) + BX * (py + BY * pz)];
+          hy += dbasis(xb, a) * sW[3 + ii][px + BX * ((2 * eb + a) + BY * pz)];
+          hz += dbasis(xc, a) * sW[6 + ii][px + BX * (py + BY * (2 * ec + a))];
         }
         H[ii][0] = hx * s2h; H[ii][1] = hy * s2h; H[ii][2] = hz * s2h;
       }
