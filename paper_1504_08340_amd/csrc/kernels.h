@@ -96,30 +96,29 @@ __device__ __forceinline__ size_t part_node(const Geo& g, const Part& P, int c, 
   return (size_t)ii + (size_t)P.nx[c] * ((size_t)jj + (size_t)P.ny[c] * kk);
 }
 
-// Offsets of a node's rows in partial array c (within one source): u-row d at
-// u + d * us, S-row v at s + v * ss.  Computed once per node before its
+// Offsets of a node's rows in partial array c (within one source).  A node's
+// rows are contiguous, so they are stored and gathered as short vectors: array
+// 0 holds the three u-rows of every node ([sn][3]) followed by the six S-rows
+// of every PML node ([sp][6]); array c != 0 holds [size_c][3] u-rows followed
+// by [size_c][6] S-rows, indexed by the node's place in the compressed box.
+// u-row d sits at u + d, S-row v at s + v.  Computed once per node before its
 // stores, so the lane-varying lookups of the array constants and face
 // ordinals are waited for once rather than once per row.
 struct RowAddr {
-  size_t u, us, s, ss;
+  size_t u, s;
 };
 
 __device__ __forceinline__ RowAddr row_addr(const Geo& g, const Part& P, int c, int i, int j, int k,
                                             size_t node, size_t p) {
   RowAddr a;
   if (c == 0) {
-    a.u = node;
-    a.us = (size_t)g.sn;
-    a.s = 3 * (size_t)g.sn + p;
-    a.ss = (size_t)g.sp;
+    a.u = 3 * node;
+    a.s = 3 * (size_t)g.sn + 6 * p;
     return a;
   }
   const size_t n = part_node(g, P, c, i, j, k);
-  const size_t size = (size_t)P.size[c];
-  a.u = (size_t)P.off[c] + n;
-  a.us = size;
-  a.s = a.u + 3 * size;
-  a.ss = size;
+  a.u = (size_t)P.off[c] + 3 * n;
+  a.s = (size_t)P.off[c] + 3 * (size_t)P.size[c] + 6 * n;
   return a;
 }
 
@@ -346,8 +345,8 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
       if (!is_dirichlet(g, i, j, k)) {
         const RowAddr ra = row_addr(g, PT, cs, i, j, k, node, 0);
         res[ra.u] = r0 * s2h;
-        res[ra.u + ra.us] = r1 * s2h;
-        res[ra.u + 2 * ra.us] = r2 * s2h;
+        res[ra.u + 1] = r1 * s2h;
+        res[ra.u + 2] = r2 * s2h;
       }
       if constexpr (GRAD) {
         sGacc[0][n] += (double)gl;
@@ -673,14 +672,14 @@ pml_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
         R q6[6];
         pml_s_rows<R, TX, TY, TZ>(cx, cy, cz, lx, ly, lz, &sQ[0][0], q6);
 #pragma unroll
-        for (int v = 0; v < 6; ++v) res[ra.s + v * ra.ss] = q6[v];
+        for (int v = 0; v < 6; ++v) res[ra.s + v] = q6[v];
       }
       if constexpr (DU) {
         if (free_u) {
           R u3[3];
           pml_u_rows<R, TX, TY, TZ>(g, cx, cy, cz, lx, ly, lz, &sT[0][0], u3);
 #pragma unroll
-          for (int ii = 0; ii < 3; ++ii) res[ra.u + ii * ra.us] = u3[ii];
+          for (int ii = 0; ii < 3; ++ii) res[ra.u + ii] = u3[ii];
         }
       }
     }
@@ -811,7 +810,7 @@ pml_gradient_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
 
 // Nodal part of one RK4 stage.  With r the element residual of the stage input
 // Y, the rates are K = (x1|PML, x2, M^{-1}(f - r - nodal PML terms)) and
-//   mode 0:  acc = Xn + cA K,  Yout = Xn + cY K
+//   mode 0:  acc = Xn + cA K,  Yout = Xn + cY K   (the stage input is Xn)
 //   mode 1:  acc += cA K,      Yout = Xn + cY K
 //   mode 2:  Xn = acc + cA K
 template <typename R>
@@ -857,30 +856,42 @@ __device__ __forceinline__ PartSlots part_slots(const Geo& g, const Part& P, int
   return S;
 }
 
-// Sum over the partial arrays of row `row` (0..2 u-rows, 3..8 S-rows); off0 is
-// the entry in array 0.  The single-axis arrays (c = 1, 2, 4) are read
-// unconditionally, at entry 0 of the array when the node is not on that face,
-// and the value is discarded by a select: the loads then issue together with
-// the others instead of one branch at a time.  Nodes on two or three faces
-// (1/32 of the nodes or fewer per array) take a branch.
-template <typename R>
-__device__ __forceinline__ R gather_rows(const Part& P, const PartSlots& S, const R* res, size_t off0, int row) {
-  R t[8];
-  t[0] = res[off0];
+// Sum over the partial arrays of a node's NR = 3 u-rows (SROWS false; base0 =
+// 3 node) or NR = 6 S-rows (SROWS true; base0 = 3 sn + 6 p), each array's rows
+// read as one contiguous vector.  The single-axis arrays (c = 1, 2, 4) are read
+// unconditionally, at their first node when the node is not on that face, and
+// the values are discarded by a select: the loads then issue together with the
+// others instead of one branch at a time.  Nodes on two or three faces (1/32
+// of the nodes or fewer per array) take a branch.
+template <typename R, int NR, bool SROWS>
+__device__ __forceinline__ void gather_rows(const Part& P, const PartSlots& S, const R* res, size_t base0,
+                                            R out[NR]) {
+  auto first = [&](int c, size_t n) {
+    return (size_t)P.off[c] + (SROWS ? 3 * (size_t)P.size[c] + 6 * n : 3 * n);
+  };
+  R t[3][NR];
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     const int c = 1 << b;
     const bool on = (S.mask & c) != 0;
-    const R v = res[(size_t)P.off[c] + (size_t)row * P.size[c] + (on ? S.nc[c] : 0)];
-    t[c] = on ? v : R(0);
+    const size_t o = first(c, on ? S.nc[c] : 0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const R v = res[o + r];
+      t[b][r] = on ? v : R(0);
+    }
   }
-  R s = t[0] + t[1] + t[2] + t[4];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) out[r] = res[base0 + r] + t[0][r] + t[1][r] + t[2][r];
   if (S.mask == 3 || S.mask == 5 || S.mask == 6 || S.mask == 7) {
 #pragma unroll
     for (int c = 3; c < 8; ++c)
-      if (c != 4 && (S.mask & c) == c) s += res[(size_t)P.off[c] + (size_t)row * P.size[c] + S.nc[c]];
+      if (c != 4 && (S.mask & c) == c) {
+        const size_t o = first(c, S.nc[c]);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) out[r] += res[o + r];
+      }
   }
-  return s;
 }
 
 // Nodal part of one stage for node rows and PML rows; MODE as described above,
@@ -916,13 +927,14 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     const bool pml = in_pml(g, i, j, k);
     const PartSlots PS = part_slots(g, A.part, i, j, k);
     R u1[3], u2[3], rr[3], x1[3], x2[3], c1[3], c2[3];
+    gather_rows<R, 3, false>(A.part, PS, res, 3 * (size_t)node, rr);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const size_t o1 = d * nn + node, o2 = (3 + d) * nn + node;
       u1[d] = Y[o1];
       u2[d] = Y[o2];
-      rr[d] = gather_rows(A.part, PS, res, o1, d);
-      if (MODE != 2) { x1[d] = __builtin_nontemporal_load(&X[o1]); x2[d] = __builtin_nontemporal_load(&X[o2]); }
+      if (MODE == 1) { x1[d] = __builtin_nontemporal_load(&X[o1]); x2[d] = __builtin_nontemporal_load(&X[o2]); }
+      if (MODE == 0) { x1[d] = u1[d]; x2[d] = u2[d]; }   // the first stage's input is Xn itself
       if (MODE != 0) { c1[d] = C[o1]; c2[d] = C[o2]; }
     }
     const R im = A.invMu[node];
@@ -1009,8 +1021,8 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     s1[v] = PY[(P_X1S + v) * np + p];
     s2[v] = PY[(P_X2S + v) * np + p];
     s0[v] = hist ? PY[(P_X0S + v) * np + p] : R(0);
-    rv[v] = gather_rows(A.part, PS, res, 3 * nn + (size_t)v * np + p, 3 + v);
   }
+  gather_rows<R, 6, true>(A.part, PS, res, 3 * nn + 6 * p, rv);
   if (hu) {
     const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
 #pragma unroll
@@ -1020,7 +1032,10 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   for (int q = 0; q < P_NCOMP; ++q) {
     const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
     const size_t o = (size_t)q * np + p;
-    if (live && MODE != 2) xv[q] = __builtin_nontemporal_load(&PX[o]);
+    if (MODE == 0 && q >= P_X0S)   // the first stage's input is Xn itself
+      xv[q] = q >= P_X2S ? s2[q - P_X2S] : (q >= P_X1S ? s1[q - P_X1S] : s0[q - P_X0S]);
+    else if (live && MODE != 2)
+      xv[q] = __builtin_nontemporal_load(&PX[o]);
     if (live && MODE != 0) cv[q] = PC[o];
   }
 #pragma unroll

@@ -234,8 +234,8 @@ interior_mfma_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, const fl
     const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
     const RowAddr ra = row_addr(g, PT, c, i, j, k, node, 0);
     res[ra.u] = r0;
-    res[ra.u + ra.us] = r1;
-    res[ra.u + 2 * ra.us] = r2;
+    res[ra.u + 1] = r1;
+    res[ra.u + 2] = r2;
   }
 }
 

@@ -806,10 +806,12 @@ __global__ void __launch_bounds__(256) power_step_kernel(Geo g, const R* __restr
     lumped_masses_tab(g, i, j, k, mrd, mp);
     const double m = rho[mi] * mrd;
     const PartSlots PS = part_slots(g, PT, i, j, k);
+    R r3[3];
+    gather_rows<R, 3, false>(PT, PS, res, 3 * (size_t)node, r3);
     for (int d = 0; d < 3; ++d) {
       const size_t o = (size_t)d * g.sn + node;
       const double x = (double)X[o] * sc;
-      const double r = (double)gather_rows(PT, PS, res, o, d) * sc;
+      const double r = (double)r3[d] * sc;
       xr += x * r;
       xm += m * x * x;
       const double y = r / m;
@@ -909,8 +911,10 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
   const bool hist = cf.nbeta >= 2;
   const PartSlots PS = part_slots(g, PT, i, j, k);
   if (!dir) {
+    R r3[3];
+    gather_rows<R, 3, false>(PT, PS, rs, 3 * (size_t)node, r3);
     for (int d = 0; d < 3; ++d) {
-      double a = -(double)invMu[node] * (double)gather_rows(PT, PS, rs, (size_t)d * nn + node, d);
+      double a = -(double)invMu[node] * (double)r3[d];
       if (pml) {
         const double kap = mp / (mrd + cf.a * mp);
         const double u0 = hist ? (double)P[(P_X0U + d) * np + p] : 0.0;
@@ -920,9 +924,11 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
     }
   }
   if (pml) {
+    R r6[6];
+    gather_rows<R, 6, true>(PT, PS, rs, 3 * nn + 6 * p, r6);
     for (int v = 0; v < 6; ++v) {
       const double s0 = hist ? (double)P[(P_X0S + v) * np + p] : 0.0;
-      O[(3 + v) * nf + node] = -(double)gather_rows(PT, PS, rs, 3 * nn + (size_t)v * np + p, 3 + v) / (cf.a * mp) -
+      O[(3 + v) * nf + node] = -(double)r6[v] / (cf.a * mp) -
                                (cf.b * (double)P[(P_X2S + v) * np + p] + cf.c * (double)P[(P_X1S + v) * np + p] +
                                 cf.d * s0) / cf.a;
     }
@@ -1061,6 +1067,7 @@ struct Run {
     static const double cA[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
     static const double cY[4] = {0.5, 0.5, 1.0, 0.0};
     static const int toff[4] = {0, 1, 1, 2};
+    if (s == 0 && Yin != Xn) return fail(p, FWI_ERR_STATE, "internal: the first RK4 stage must start from Xn");
     const Geo& G = g();
     const double dt = p->prob.dt;
     NodalArgs<R> A{};
