@@ -44,6 +44,22 @@ namespace pmlfwi {
 
 enum { P_X0U = 0, P_X0S = 3, P_X1S = 9, P_X2S = 15, P_NCOMP = 21, U_NCOMP = 6 };
 
+// State register of one source.  Node part: x1 u as [sn][3], then x2 u as
+// [sn][3]; PML part (from entry 6 sn): x0 u as [sp][3], then x0 S, x1 S and
+// x2 S as [sp][6] each.  A field's components at a node are contiguous, so a
+// kernel loads or stores them as one vector.
+// Entry of u-component d (0..2: x1 u, 3..5: x2 u) of node `node`:
+__host__ __device__ __forceinline__ size_t u_at(size_t nn, int d, size_t node) {
+  return d < 3 ? 3 * node + d : 3 * nn + 3 * node + (d - 3);
+}
+// Entry of PML component q (P_X0U .. P_NCOMP-1) of PML node p, relative to
+// the PML part:
+__host__ __device__ __forceinline__ size_t p_at(size_t np, int q, size_t p) {
+  if (q < P_X0S) return 3 * p + q;
+  const int b = q < P_X1S ? P_X0S : (q < P_X2S ? P_X1S : P_X2S);
+  return (size_t)b * np + 6 * p + (q - b);
+}
+
 // Voigt slot of the symmetric pair (i, k).
 __host__ __device__ constexpr int vidx(int i, int k) { return i == k ? i : 6 - i - k; }
 
@@ -228,11 +244,11 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
     const R* Yu = Ybase + (size_t)src * ystride;
     if (live) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sU[d][n] = Yu[d * nn + node];
+      for (int d = 0; d < 3; ++d) sU[d][n] = Yu[u_at(nn, d, node)];
       if constexpr (GRAD) {
         const R* F = fwd + (size_t)src * fstride;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sV[d][n] = F[(size_t)d * g.si + mi];
+        for (int d = 0; d < 3; ++d) sV[d][n] = F[3 * (size_t)mi + d];
       }
     }
     __syncthreads();
@@ -398,17 +414,17 @@ __device__ __forceinline__ void pml_load_node(const R* __restrict__ Y, size_t nn
   if constexpr (U) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      v.u1[d] = Y[d * nn + gnode];
-      v.u2[d] = Y[(3 + d) * nn + gnode];
-      v.u0[d] = hist ? P[(P_X0U + d) * np + gp] : R(0);
+      v.u1[d] = Y[u_at(nn, d, gnode)];
+      v.u2[d] = Y[u_at(nn, 3 + d, gnode)];
+      v.u0[d] = hist ? P[p_at(np, P_X0U + d, gp)] : R(0);
     }
   }
   if constexpr (S) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      v.s1[c] = P[(P_X1S + c) * np + gp];
-      v.s2[c] = P[(P_X2S + c) * np + gp];
-      v.s0[c] = hist ? P[(P_X0S + c) * np + gp] : R(0);
+      v.s1[c] = P[p_at(np, P_X1S + c, gp)];
+      v.s2[c] = P[p_at(np, P_X2S + c, gp)];
+      v.s0[c] = hist ? P[p_at(np, P_X0S + c, gp)] : R(0);
     }
   }
 }
@@ -744,7 +760,7 @@ pml_gradient_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int nsrc,
       }
       pml_node_w<R, NB>(v, Le, Lp, Lw, n, sW);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sZ[c][n] = P[(P_X1S + c) * np + gp];
+      for (int c = 0; c < 6; ++c) sZ[c][n] = P[p_at(np, P_X1S + c, gp)];
     }
     __syncthreads();
     for (int q = threadIdx.x; q < NP; q += blockDim.x) {
@@ -829,7 +845,7 @@ struct NodalArgs {
   const double* src_dir;      // (nsrc, 3)
   const double* wav;          // (nsrc, wav_len)
   int wav_len, wav_idx;
-  R* store;                   // x1 displacement of the produced register on the
+  R* store;                   // x1 displacement ([si][3]) of the produced register on the
   long long store_stride;     // interior closure (per source stride), or nullptr
   R* pstore;                  // PML displacement fields of the produced register
   long long pstore_stride;    // [x1 u | x2 u | x0 u] x sp per source, or nullptr
@@ -928,14 +944,27 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
     const PartSlots PS = part_slots(g, A.part, i, j, k);
     R u1[3], u2[3], rr[3], x1[3], x2[3], c1[3], c2[3];
     gather_rows<R, 3, false>(A.part, PS, res, 3 * (size_t)node, rr);
+    const size_t o1 = u_at(nn, 0, node), o2 = u_at(nn, 3, node);   // x1 u, x2 u of the node
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const size_t o1 = d * nn + node, o2 = (3 + d) * nn + node;
-      u1[d] = Y[o1];
-      u2[d] = Y[o2];
-      if (MODE == 1) { x1[d] = __builtin_nontemporal_load(&X[o1]); x2[d] = __builtin_nontemporal_load(&X[o2]); }
-      if (MODE == 0) { x1[d] = u1[d]; x2[d] = u2[d]; }   // the first stage's input is Xn itself
-      if (MODE != 0) { c1[d] = C[o1]; c2[d] = C[o2]; }
+      u1[d] = Y[o1 + d];
+      u2[d] = Y[o2 + d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (MODE == 1) x1[d] = __builtin_nontemporal_load(&X[o1 + d]);
+      if (MODE == 0) x1[d] = u1[d];   // the first stage's input is Xn itself
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (MODE == 1) x2[d] = __builtin_nontemporal_load(&X[o2 + d]);
+      if (MODE == 0) x2[d] = u2[d];
+    }
+    if (MODE != 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) c1[d] = C[o1 + d];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) c2[d] = C[o2 + d];
     }
     const R im = A.invMu[node];
     R a2[3];
@@ -954,27 +983,38 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
       R u0[3] = {0, 0, 0};
       if (c.nbeta >= 2) {
         const size_t p = (size_t)pml_index(g, i, j, k);
-        const R* P = Y + 6 * nn;
+        const R* P = Y + 6 * nn + p_at(np, P_X0U, p);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) u0[d] = P[(P_X0U + d) * np + p];
+        for (int d = 0; d < 3; ++d) u0[d] = P[d];
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d)
         a2[d] -= kap * (R(c.b) * u2[d] + R(c.c) * u1[d] + R(c.d) * u0[d]);
     }
-    R out1[3], out2[3];
+    // each field's three components are stored together (one vector store)
+    R out1[3], out2[3], n1[3], n2[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const size_t o1 = d * nn + node, o2 = (3 + d) * nn + node;
       if (MODE == 2) {
-        X[o1] = out1[d] = c1[d] + cA * u2[d];
-        X[o2] = out2[d] = c2[d] + cA * a2[d];
+        out1[d] = c1[d] + cA * u2[d];
+        out2[d] = c2[d] + cA * a2[d];
       } else {
-        __builtin_nontemporal_store((MODE == 0 ? x1[d] : c1[d]) + cA * u2[d], &C[o1]);
-        __builtin_nontemporal_store((MODE == 0 ? x2[d] : c2[d]) + cA * a2[d], &C[o2]);
-        Yo[o1] = out1[d] = x1[d] + cY * u2[d];
-        Yo[o2] = out2[d] = x2[d] + cY * a2[d];
+        n1[d] = (MODE == 0 ? x1[d] : c1[d]) + cA * u2[d];
+        n2[d] = (MODE == 0 ? x2[d] : c2[d]) + cA * a2[d];
+        out1[d] = x1[d] + cY * u2[d];
+        out2[d] = x2[d] + cY * a2[d];
       }
+    }
+    R* const D = MODE == 2 ? X : Yo;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) D[o1 + d] = out1[d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) D[o2 + d] = out2[d];
+    if (MODE != 2) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) __builtin_nontemporal_store(n1[d], &C[o1 + d]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) __builtin_nontemporal_store(n2[d], &C[o2 + d]);
     }
     if (STORE == 2 && pml) {
       R* PS_ = A.pstore + (size_t)src * A.pstore_stride;
@@ -990,7 +1030,7 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
       if (mi >= 0) {
         R* S = A.store + (size_t)src * A.store_stride;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) S[(size_t)d * g.si + mi] = out1[d];
+        for (int d = 0; d < 3; ++d) S[3 * (size_t)mi + d] = out1[d];
       }
     }
     return;
@@ -1013,54 +1053,82 @@ __global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const R ia = R(1) / R(c.a), iam = R(1) / (R(c.a) * R(mp));
   const R cb = R(c.b), cc = R(c.c), cd = R(c.d);
 
-  // rates of the 21 PML components, then one pass of register updates
-  R rate[P_NCOMP], xv[P_NCOMP], cv[P_NCOMP];
+  // Rates of the PML components, then the register updates, one field at a
+  // time (x0 u: 3 components, on history nodes off the Dirichlet boundary;
+  // x0 S: 6, on history nodes; x1 S, x2 S: 6 each), so that a field's
+  // components move with one vector load or store.
+  const size_t b0u = p_at(np, P_X0U, p), b0s = p_at(np, P_X0S, p);
+  const size_t b1s = p_at(np, P_X1S, p), b2s = p_at(np, P_X2S, p);
   R s0[6], s1[6], s2[6], rv[6], y1[3];
 #pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    s1[v] = PY[(P_X1S + v) * np + p];
-    s2[v] = PY[(P_X2S + v) * np + p];
-    s0[v] = hist ? PY[(P_X0S + v) * np + p] : R(0);
+  for (int v = 0; v < 6; ++v) s1[v] = PY[b1s + v];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) s2[v] = PY[b2s + v];
+  if (hist) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) s0[v] = PY[b0s + v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) s0[v] = R(0);
   }
   gather_rows<R, 6, true>(A.part, PS, res, 3 * nn + 6 * p, rv);
   if (hu) {
     const size_t node = (size_t)i + (size_t)g.NX * (j + (size_t)g.NY * k);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) y1[d] = Y[d * nn + node];
+    for (int d = 0; d < 3; ++d) y1[d] = Y[u_at(nn, 0, node) + d];
   }
+  // register values of one field: Xn (mode 0: the stage input) and acc
+  auto fetch = [&](size_t b, const R* in, auto& xv, auto& cv) {
+    constexpr int n = sizeof(xv) / sizeof(R);
 #pragma unroll
-  for (int q = 0; q < P_NCOMP; ++q) {
-    const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
-    const size_t o = (size_t)q * np + p;
-    if (MODE == 0 && q >= P_X0S)   // the first stage's input is Xn itself
-      xv[q] = q >= P_X2S ? s2[q - P_X2S] : (q >= P_X1S ? s1[q - P_X1S] : s0[q - P_X0S]);
-    else if (live && MODE != 2)
-      xv[q] = __builtin_nontemporal_load(&PX[o]);
-    if (live && MODE != 0) cv[q] = PC[o];
-  }
-#pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    rate[P_X0S + v] = s1[v];
-    rate[P_X1S + v] = s2[v];
-    rate[P_X2S + v] = -rv[v] * iam - ia * (cb * s2[v] + cc * s1[v] + cd * s0[v]);
-  }
-#pragma unroll
-  for (int d = 0; d < 3; ++d) rate[P_X0U + d] = hu ? y1[d] : R(0);
-#pragma unroll
-  for (int q = 0; q < P_NCOMP; ++q) {
-    const bool live = q >= P_X1S || (q >= P_X0S ? hist : hu);
-    if (!live) continue;
-    const size_t o = (size_t)q * np + p;
-    R outv;
-    if (MODE == 2) {
-      PX[o] = outv = cv[q] + cA * rate[q];
-    } else {
-      __builtin_nontemporal_store((MODE == 0 ? xv[q] : cv[q]) + cA * rate[q], &PC[o]);
-      PO[o] = outv = xv[q] + cY * rate[q];
+    for (int q = 0; q < n; ++q) {
+      if (MODE == 0) xv[q] = in ? in[q] : __builtin_nontemporal_load(&PX[b + q]);
+      if (MODE == 1) xv[q] = __builtin_nontemporal_load(&PX[b + q]);
     }
-    if (STORE == 2 && q < P_X0S)   // x0 u of a history node
-      A.pstore[(size_t)src * A.pstore_stride + (size_t)(6 + q - P_X0U) * np + p] = outv;
+    if (MODE != 0) {
+#pragma unroll
+      for (int q = 0; q < n; ++q) cv[q] = PC[b + q];
+    }
+  };
+  // stage combination of one field with its rates; out: the produced value
+  auto update = [&](size_t b, const auto& xv, const auto& cv, const auto& rate, auto& out) {
+    constexpr int n = sizeof(xv) / sizeof(R);
+    R na[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      if (MODE == 2) {
+        out[q] = cv[q] + cA * rate[q];
+      } else {
+        na[q] = (MODE == 0 ? xv[q] : cv[q]) + cA * rate[q];
+        out[q] = xv[q] + cY * rate[q];
+      }
+    }
+    R* const D = MODE == 2 ? PX : PO;
+#pragma unroll
+    for (int q = 0; q < n; ++q) D[b + q] = out[q];
+    if (MODE != 2) {
+#pragma unroll
+      for (int q = 0; q < n; ++q) __builtin_nontemporal_store(na[q], &PC[b + q]);
+    }
+  };
+  R x0u[3], c0u[3], x0s[6], c0s[6], x1s[6], c1s[6], x2s[6], c2s[6];
+  if (hu) fetch(b0u, nullptr, x0u, c0u);
+  if (hist) fetch(b0s, s0, x0s, c0s);
+  fetch(b1s, s1, x1s, c1s);
+  fetch(b2s, s2, x2s, c2s);
+  R r2s[6], o6[6], o3[3];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) r2s[v] = -rv[v] * iam - ia * (cb * s2[v] + cc * s1[v] + cd * s0[v]);
+  if (hu) {
+    update(b0u, x0u, c0u, y1, o3);
+    if (STORE == 2) {   // x0 u of a history node
+#pragma unroll
+      for (int d = 0; d < 3; ++d) A.pstore[(size_t)src * A.pstore_stride + (size_t)(6 + d) * np + p] = o3[d];
+    }
   }
+  if (hist) update(b0s, x0s, c0s, s1, o6);
+  update(b1s, x1s, c1s, s2, o6);
+  update(b2s, x2s, c2s, r2s, o6);
 }
 
 // 1/M_uu at every node (0 on Dirichlet nodes): rho (m_rd + a m_p).

@@ -129,7 +129,7 @@ interior_mfma_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, const fl
       sLam[n] = lam[mi];
       sMu[n] = mu[mi];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sU[d][n] = Yu[d * nn + node];
+      for (int d = 0; d < 3; ++d) sU[d][n] = Yu[u_at(nn, d, node)];
     } else {
       sLam[n] = 0.0f;
       sMu[n] = 0.0f;

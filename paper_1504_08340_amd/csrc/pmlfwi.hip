@@ -526,7 +526,7 @@ __global__ void receivers_kernel(const R* __restrict__ X, long long reg, int sn,
   const R* U = X + (size_t)src * reg;
   double* T = traces + ((size_t)src * (nsteps + 1) + step) * nrec * 3 + (size_t)r * 3;
   const int node = rec[r];
-  for (int d = 0; d < 3; ++d) T[d] = (double)U[(size_t)d * sn + node];
+  for (int d = 0; d < 3; ++d) T[d] = (double)U[u_at(sn, d, node)];
 }
 
 // Adjoint impulse after a reverse step: y2_u += M^{-1} dt w_n (u^n - u_m^n) at receivers.
@@ -540,7 +540,7 @@ __global__ void impulse_kernel(R* __restrict__ Y, long long reg, int sn, const R
   const double* E = resid + ((size_t)src * (nsteps + 1) + step) * nrec * 3 + (size_t)r * 3;
   const int node = rec[r];
   const R im = invMu[node];
-  for (int d = 0; d < 3; ++d) atomic_add(&U[(size_t)(3 + d) * sn + node], R(scale * E[d]) * im);
+  for (int d = 0; d < 3; ++d) atomic_add(&U[u_at(sn, 3 + d, node)], R(scale * E[d]) * im);
 }
 
 // Receiver forcing of the paper's reverse RK4 (App. B) in one stage.  With
@@ -562,7 +562,7 @@ __global__ void appb_force_kernel(R* __restrict__ Yout, R* __restrict__ Xn, R* _
   const double im = (double)invMu[node];
   for (int d = 0; d < 3; ++d) {
     const double gval = -im * (a_hi * Eh[d] + a_lo * El[d]);
-    const size_t o = off + (size_t)(3 + d) * sn + node;
+    const size_t o = off + u_at(sn, 3 + d, node);
     if (mode == 2) {
       atomic_add(&Xn[o], R(cA * gval));
     } else {
@@ -596,7 +596,7 @@ __global__ void load_kernel(R* __restrict__ Yout, R* __restrict__ Xn, R* __restr
   const size_t off = (size_t)src * reg;
   for (int d = 0; d < 3; ++d) {
     const double g = im * lvec[3 * e + d] * f;
-    const size_t o = off + (size_t)(3 + d) * sn + node;
+    const size_t o = off + u_at(sn, 3 + d, node);
     if (mode == 2) {
       Xn[o] += R(cA * g);
     } else {
@@ -649,7 +649,7 @@ __global__ void extract_kernel(Geo g, const R* __restrict__ X, long long reg, R*
   const int jz = mi / (g.NIX * g.NIY), rr = mi - jz * g.NIX * g.NIY, jy = rr / g.NIX, jx = rr - jy * g.NIX;
   const size_t node = (size_t)(jx + 2 * g.ps) + (size_t)g.NX * ((jy + 2 * g.ps) + (size_t)g.NY * (jz + 2 * g.pb));
   for (int d = 0; d < 3; ++d)
-    S[(size_t)src * sstr + (size_t)d * g.si + mi] = X[(size_t)src * reg + (size_t)d * g.sn + node];
+    S[(size_t)src * sstr + 3 * (size_t)mi + d] = X[(size_t)src * reg + u_at(g.sn, d, node)];
 }
 
 // PML displacement fields of a register -> stored-stage slot [x1 u | x2 u | x0 u] x sp
@@ -667,9 +667,9 @@ __global__ void pextract_kernel(Geo g, const R* __restrict__ X, long long reg, R
   const bool dir = is_dirichlet(g, i, j, k);
   const bool hist = !dir && pml_coef_tab(g, i, j, k).nbeta >= 2;
   for (int d = 0; d < 3; ++d) {
-    D[(size_t)d * g.sp + p] = dir ? R(0) : U[(size_t)d * g.sn + node];
-    D[(size_t)(3 + d) * g.sp + p] = dir ? R(0) : U[(size_t)(3 + d) * g.sn + node];
-    D[(size_t)(6 + d) * g.sp + p] = hist ? P[(size_t)(P_X0U + d) * g.sp + p] : R(0);
+    D[(size_t)d * g.sp + p] = dir ? R(0) : U[u_at(g.sn, d, node)];
+    D[(size_t)(3 + d) * g.sp + p] = dir ? R(0) : U[u_at(g.sn, 3 + d, node)];
+    D[(size_t)(6 + d) * g.sp + p] = hist ? P[p_at(g.sp, P_X0U + d, p)] : R(0);
   }
 }
 
@@ -809,7 +809,7 @@ __global__ void __launch_bounds__(256) power_step_kernel(Geo g, const R* __restr
     R r3[3];
     gather_rows<R, 3, false>(PT, PS, res, 3 * (size_t)node, r3);
     for (int d = 0; d < 3; ++d) {
-      const size_t o = (size_t)d * g.sn + node;
+      const size_t o = u_at(g.sn, d, node);
       const double x = (double)X[o] * sc;
       const double r = (double)r3[d] * sc;
       xr += x * r;
@@ -864,7 +864,7 @@ __global__ void power_init_kernel(Geo g, R* __restrict__ X, double* __restrict__
   if (node >= g.n_nodes) return;
   const int k = node / g.plane, r_ = node - k * g.plane, j = r_ / g.NX, i = r_ - j * g.NX;
   const bool on = !is_dirichlet(g, i, j, k) && interior_index(g, i, j, k) >= 0;
-  for (int d = 0; d < 3; ++d) X[(size_t)d * g.sn + node] = on ? R(power_start((unsigned)node, d)) : R(0);
+  for (int d = 0; d < 3; ++d) X[u_at(g.sn, d, node)] = on ? R(power_start((unsigned)node, d)) : R(0);
 }
 
 // Nodal test fields [nsrc][9][n_nodes] <-> register slot (0: x0, 1: x1, 2: x2).
@@ -881,12 +881,12 @@ __global__ void pack_kernel(Geo g, const double* __restrict__ in, R* __restrict_
   const size_t p = pml ? (size_t)pml_index(g, i, j, k) : 0;
   for (int d = 0; d < 3; ++d) {
     const R v = dir ? R(0) : R(F[d * nf + node]);
-    if (slot == 0) { if (pml) P[(P_X0U + d) * np + p] = v; }
-    else U[(size_t)(slot == 1 ? d : 3 + d) * nn + node] = v;
+    if (slot == 0) { if (pml) P[p_at(np, P_X0U + d, p)] = v; }
+    else U[u_at(nn, slot == 1 ? d : 3 + d, node)] = v;
   }
   if (pml) {
     const int base = slot == 0 ? P_X0S : (slot == 1 ? P_X1S : P_X2S);
-    for (int v = 0; v < 6; ++v) P[(base + v) * np + p] = R(F[(3 + v) * nf + node]);
+    for (int v = 0; v < 6; ++v) P[p_at(np, base + v, p)] = R(F[(3 + v) * nf + node]);
   }
 }
 
@@ -917,8 +917,8 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
       double a = -(double)invMu[node] * (double)r3[d];
       if (pml) {
         const double kap = mp / (mrd + cf.a * mp);
-        const double u0 = hist ? (double)P[(P_X0U + d) * np + p] : 0.0;
-        a -= kap * (cf.b * (double)U[(3 + d) * nn + node] + cf.c * (double)U[d * nn + node] + cf.d * u0);
+        const double u0 = hist ? (double)P[p_at(np, P_X0U + d, p)] : 0.0;
+        a -= kap * (cf.b * (double)U[u_at(nn, 3 + d, node)] + cf.c * (double)U[u_at(nn, d, node)] + cf.d * u0);
       }
       O[d * nf + node] = a;
     }
@@ -927,9 +927,9 @@ __global__ void accel_kernel(Geo g, const R* __restrict__ Y, long long reg, cons
     R r6[6];
     gather_rows<R, 6, true>(PT, PS, rs, 3 * nn + 6 * p, r6);
     for (int v = 0; v < 6; ++v) {
-      const double s0 = hist ? (double)P[(P_X0S + v) * np + p] : 0.0;
+      const double s0 = hist ? (double)P[p_at(np, P_X0S + v, p)] : 0.0;
       O[(3 + v) * nf + node] = -(double)r6[v] / (cf.a * mp) -
-                               (cf.b * (double)P[(P_X2S + v) * np + p] + cf.c * (double)P[(P_X1S + v) * np + p] +
+                               (cf.b * (double)P[p_at(np, P_X2S + v, p)] + cf.c * (double)P[p_at(np, P_X1S + v, p)] +
                                 cf.d * s0) / cf.a;
     }
   }
