@@ -7,10 +7,12 @@ random lam, mu of the throughput workload, its first source (8 Hz Ricker at
 (-10, -10, 0)), all 6,561 receivers, 400 RK4 steps, observed data zero.  The
 GPU runs the launch configuration bench.py times (5x4x2 brick tiles,
 512-thread element workgroups, stage displacements kept) in every precision:
-traces within 1e-5 (relative L2 over the stored receivers), misfit within
-1e-5, lam and mu gradients within 1e-4 (relative L2 over the stored nodes,
-and the norms of the full vectors); FP64 to rounding (1e-11 / 1e-9).  The
-4-source batch the bench times gives the same source-1 traces.
+traces and misfit within 2e-6 (relative L2 over the stored receivers), lam
+and mu gradients within 1e-6 (relative L2 over the stored nodes, and the
+norms of the full vectors); FP64 to rounding (1e-13 / 1e-12).  Observed:
+FP64 4e-16 traces, 7e-15 gradients; FP32, FP32-MFMA and split-BF16 1.7e-7 to
+1.8e-7 traces, 2e-8 to 6e-8 gradients.  The 4-source batch the bench times
+gives the same source-1 traces.
 """
 import os
 
@@ -57,7 +59,7 @@ def _run(P, wl, prec, nsrc):
     return out
 
 
-@pytest.mark.parametrize("prec,ttol,gtol", [(0, 1e-11, 1e-9), (1, 1e-5, 1e-4), (2, 1e-5, 1e-4), (3, 1e-5, 1e-4)])
+@pytest.mark.parametrize("prec,ttol,gtol", [(0, 1e-13, 1e-12), (1, 2e-6, 1e-6), (2, 2e-6, 1e-6), (3, 2e-6, 1e-6)])
 def test_cfg2_400_steps_vs_oracle_fixture(P, ref, prec, ttol, gtol):
     wl = W.config2(nsteps=int(ref["nsteps"]))
     assert wl.prob.dt == float(ref["dt"])
@@ -78,4 +80,4 @@ def test_cfg2_400_steps_four_source_batch(P, ref):
     tr, _, _, _ = _run(P, wl, 1, 4)
     e = _rel(tr[0][:, ref["traces_rec"], :], ref["traces"])
     print(f"4-source FP32 batch, source 1 traces: {e:.2e}")
-    assert e <= 1e-5
+    assert e <= 2e-6
