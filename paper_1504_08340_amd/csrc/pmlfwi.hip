@@ -998,8 +998,46 @@ struct Run {
   // The interior and PML bricks write disjoint partial-array entries, so the
   // two launches may run at the same time: the interior one goes to the plan's
   // second stream when both lists are non-empty.
+  // PML rows on the matrix cores for the FP32-state precisions that ask for it
+  // (one source per workgroup, one row type per launch); false when the scalar
+  // kernel is to be used.
+  template <int PART>
+  bool mfma_pml(bool adj, unsigned gx, int nt, const R* Y, long long reg, hipStream_t sp) {
+    if constexpr (std::is_same<R, float>::value) {
+      const int pr = p->prob.precision;
+      if (pr != FWI_FP32_MFMA && pr != FWI_FP32_BF16X3) return false;
+      if constexpr (PART == PML_ALL) {
+        mfma_pml<PML_UROWS>(adj, gx, nt, Y, reg, sp);
+        mfma_pml<PML_SROWS>(adj, gx, nt, Y, reg, sp);
+      } else {
+        const dim3 grid(gx, p->nsrc);
+        const Tile* T = p->d_tiles_pml;
+        if (pr == FWI_FP32_MFMA) {
+          constexpr int th = mfma_threads(MFMA_F32);
+          if (adj)
+            pml_mfma_kernel<MFMA_F32, TX, TY, TZ, true, PART><<<grid, th, 0, sp>>>(g(), T, nt, Y, reg, lam(), mu(),
+                                                                                 res(), L.part);
+          else
+            pml_mfma_kernel<MFMA_F32, TX, TY, TZ, false, PART><<<grid, th, 0, sp>>>(g(), T, nt, Y, reg, lam(), mu(),
+                                                                                  res(), L.part);
+        } else {
+          constexpr int th = mfma_threads(MFMA_BF16X3);
+          if (adj)
+            pml_mfma_kernel<MFMA_BF16X3, TX, TY, TZ, true, PART><<<grid, th, 0, sp>>>(g(), T, nt, Y, reg, lam(),
+                                                                                    mu(), res(), L.part);
+          else
+            pml_mfma_kernel<MFMA_BF16X3, TX, TY, TZ, false, PART><<<grid, th, 0, sp>>>(g(), T, nt, Y, reg, lam(),
+                                                                                     mu(), res(), L.part);
+        }
+      }
+      return true;
+    }
+    return false;
+  }
+
   template <int PART>
   void launch_pml(bool adj, dim3 grid, int nt, const R* Y, long long reg, hipStream_t sp) {
+    if (mfma_pml<PART>(adj, grid.x, nt, Y, reg, sp)) return;
     if (adj)
       pml_element_kernel<R, TX, TY, TZ, true, SRCLOOP, PART><<<grid, ETHREADS, 0, sp>>>(
           g(), p->d_tiles_pml, nt, p->nsrc, Y, reg, lam(), mu(), res(), L.part);
