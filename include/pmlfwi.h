@@ -77,9 +77,10 @@ typedef enum {
   FWI_FP64 = 0,           /* state, element arithmetic and accumulation in FP64 */
   FWI_FP32 = 1,           /* state and element arithmetic in FP32; misfit and
                              gradient time integrals accumulated in FP64 */
-  FWI_FP32_MFMA = 2,      /* as FWI_FP32, with the interior stiffness applied as
-                             dense reference-matrix contractions on the matrix
-                             cores (FP32 MFMA) */
+  FWI_FP32_MFMA = 2,      /* as FWI_FP32, with the interior stiffness and the PML
+                             operator of the forward and transposed stages applied
+                             as dense reference-matrix contractions on the matrix
+                             cores (FP32 MFMA); the gradient terms stay scalar */
   FWI_FP32_BF16X3 = 3     /* as FWI_FP32_MFMA, on BF16 MFMA: the FP32 operand
                              split into three BF16 parts, FP32 accumulation */
 } fwi_precision;
