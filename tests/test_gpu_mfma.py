@@ -1,7 +1,8 @@
-"""Interior stiffness on the matrix cores (FWI_FP32_MFMA, FWI_FP32_BF16X3).
+"""Interior stiffness and PML operator on the matrix cores (FWI_FP32_MFMA,
+FWI_FP32_BF16X3).
 
-The dense reference-matrix form must give the operator of the scalar
-kernels: one application against the FP64 oracle at FP32 rounding level
+The dense reference-matrix forms must give the operator of the scalar
+kernels (interior and PML rows, forward and transposed): one application against the FP64 oracle at FP32 rounding level
 (ragged tiles, several sources), then forward, misfit and gradient against
 the oracle at the FP32 tolerances (traces 1e-5, gradients 1e-4), on
 the 864-brick workload and, for 3 steps, on the 62,500-brick mesh.
