@@ -2,7 +2,7 @@
 
 python -m paper_1504_08340_amd.fwi_run [--nsteps N] [--freqs 4,8,12]
         [--iters K] [--precision fp32|fp64] [--reg tikhonov|tv]
-        [--target-frac F] [--start trend|file.npz]
+        [--target-frac F] [--start trend|file.npz] [--full-gradient]
 
 Model: three layers (vs 120 / 200 / 300 m/s, boundaries at 5 and 11 m
 depth) and a 4x4x3 m soft block (vs 90 m/s), vp = 2 vs, rho = 2000; nine
@@ -33,7 +33,8 @@ def build(args):
     from . import FWI_FP32, FWI_FP64, Solver
     wl = W.config3(nsteps=args.nsteps)
     prec = FWI_FP32 if args.precision == "fp32" else FWI_FP64
-    S = Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node, precision=prec, ckpt_every=args.ckpt)
+    S = Solver(wl.prob, wl.src_node, wl.src_dir, wl.rec_node, precision=prec, ckpt_every=args.ckpt,
+               grad_full=args.full_gradient)
     rho = S.tensor(wl.rho)
     lam_t, mu_t = S.tensor(wl.lam_true), S.tensor(wl.mu_true)
     stages = []
@@ -101,6 +102,9 @@ def main(argv=None):
     ap.add_argument("--tv-eps", type=float, default=1e10)
     ap.add_argument("--target-frac", type=float, default=1e-2)
     ap.add_argument("--start", default="trend")
+    ap.add_argument("--full-gradient", action="store_true",
+                    help="chain rule through the material carried into the PML instead of the gradient "
+                         "restricted to the interior bricks (Sec. 3.1.3)")
     args = ap.parse_args(argv)
     import torch
     wl, S, rho, stages = build(args)
@@ -113,6 +117,7 @@ def main(argv=None):
     res.update(metric="FWI time to target misfit", workload="32x32x16 m layered + block, 9 sources, "
                f"{args.nsteps} steps, fc {','.join(str(f) for f in args.freqs)} Hz",
                precision=args.precision, start=args.start, iters_per_stage=args.iters,
+               grad_full=bool(args.full_gradient), reg=args.reg,
                device=torch.cuda.get_device_name(0))
     print(json.dumps(res), flush=True)
 
