@@ -39,6 +39,10 @@
 #ifndef PMLFWI_ETHREADS
 #define PMLFWI_ETHREADS 512
 #endif
+// Threads per nodal workgroup (128 measured a little faster than 256, 512 slower).
+#ifndef PMLFWI_NODAL_THREADS
+#define PMLFWI_NODAL_THREADS 128
+#endif
 
 namespace pmlfwi {
 
@@ -920,7 +924,7 @@ __device__ __forceinline__ void gather_rows(const Part& P, const PartSlots& S, c
 // pass, so they should not displace the stage input and the residual partials
 // that the element kernels and this kernel share in the caches.
 template <typename R, int MODE, int STORE>
-__global__ void __launch_bounds__(256) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
+__global__ void __launch_bounds__(PMLFWI_NODAL_THREADS) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
   const unsigned blk = A.rot ? (blockIdx.x + A.rot) % gridDim.x : blockIdx.x;
   const long long gid = A.first + (long long)blk * blockDim.x + threadIdx.x;

@@ -1130,19 +1130,20 @@ struct Run {
           {nodal_rk_kernel<R, 1, 0>, nodal_rk_kernel<R, 1, 1>, nodal_rk_kernel<R, 1, 2>},
           {nodal_rk_kernel<R, 2, 0>, nodal_rk_kernel<R, 2, 1>, nodal_rk_kernel<R, 2, 2>}};
       const K kern = table[A.mode][sm];
+      constexpr int NT = PMLFWI_NODAL_THREADS;
       if (PMLFWI_NODAL_ORDER == 2) {
         A.first = 0;
         A.last = G.sn;
-        kern<<<dim3(blocks((size_t)G.sn, 256), p->nsrc), 256, 0, st>>>(G, A);
+        kern<<<dim3(blocks((size_t)G.sn, NT), p->nsrc), NT, 0, st>>>(G, A);
         A.first = G.sn;
         A.last = rows;
-        kern<<<dim3(blocks((size_t)G.n_pml, 256), p->nsrc), 256, 0, st>>>(G, A);
+        kern<<<dim3(blocks((size_t)G.n_pml, NT), p->nsrc), NT, 0, st>>>(G, A);
       } else {
-        const unsigned nb = (unsigned)blocks((size_t)rows, 256);
+        const unsigned nb = (unsigned)blocks((size_t)rows, NT);
         A.first = 0;
         A.last = rows;
-        A.rot = PMLFWI_NODAL_ORDER == 1 ? (unsigned)(G.sn / 256) % nb : 0u;
-        kern<<<dim3(nb, p->nsrc), 256, 0, st>>>(G, A);
+        A.rot = PMLFWI_NODAL_ORDER == 1 ? (unsigned)(G.sn / NT) % nb : 0u;
+        kern<<<dim3(nb, p->nsrc), NT, 0, st>>>(G, A);
       }
     }
     if (wav && p->nload > 0) {
