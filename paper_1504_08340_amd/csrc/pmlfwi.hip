@@ -235,7 +235,9 @@ namespace {
 #endif
 // PML operator as two launches, one per row type (smaller LDS and register
 // footprints, 8 waves per SIMD; they interleave with the interior launch on
-// the other stream), u-rows first, rather than one launch for both.
+// the other stream), rather than one launch for both.  Forward stages launch
+// the S-rows first, transposed stages the u-rows first: in each order the PML
+// pair and the interior launch beside it end closest together.
 #ifndef PMLFWI_PML_SPLIT
 #define PMLFWI_PML_SPLIT 1
 #endif
@@ -244,8 +246,11 @@ namespace {
 #ifndef PMLFWI_NODAL_ORDER
 #define PMLFWI_NODAL_ORDER 1
 #endif
-#ifndef PMLFWI_SPLIT_FIRST
-#define PMLFWI_SPLIT_FIRST PML_UROWS
+#ifndef PMLFWI_SPLIT_FIRST_FWD
+#define PMLFWI_SPLIT_FIRST_FWD PML_SROWS
+#endif
+#ifndef PMLFWI_SPLIT_FIRST_ADJ
+#define PMLFWI_SPLIT_FIRST_ADJ PML_UROWS
 #endif
 #ifndef PMLFWI_CONCURRENT
 #define PMLFWI_CONCURRENT 1
@@ -1080,8 +1085,13 @@ struct Run {
       if (PMLFWI_PML_SPLIT) {
         // the two row types write disjoint rows: with three streams the
         // second part runs beside the first and the interior bricks
-        launch_pml<PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg, st);
-        launch_pml<PML_ALL ^ PMLFWI_SPLIT_FIRST>(adj, grid, nt, Y, reg, fork2 ? p->side2 : st);
+        if (adj) {
+          launch_pml<PMLFWI_SPLIT_FIRST_ADJ>(adj, grid, nt, Y, reg, st);
+          launch_pml<PML_ALL ^ PMLFWI_SPLIT_FIRST_ADJ>(adj, grid, nt, Y, reg, fork2 ? p->side2 : st);
+        } else {
+          launch_pml<PMLFWI_SPLIT_FIRST_FWD>(adj, grid, nt, Y, reg, st);
+          launch_pml<PML_ALL ^ PMLFWI_SPLIT_FIRST_FWD>(adj, grid, nt, Y, reg, fork2 ? p->side2 : st);
+        }
         if (fork2) HIP_TRY(p, hipEventRecord(p->join2_ev, p->side2));
       } else {
         launch_pml<PML_ALL>(adj, grid, nt, Y, reg, st);
