@@ -125,16 +125,19 @@ def pass_bytes_per_dof_step(sizes, prob, nsrc, es, n_hist):
     """Compulsory HBM bytes of one forward + adjoint + gradient pass that keeps
     the stage displacements (no recompute), per DOF-step.
 
-    Per RK4 stage and source, three-register classical RK4 streams the state
-    five times (stage input, Xn, accumulator read and write, next stage):
-    5 n_X with n_X = n_hist + 2 n_state; the forward writes and the adjoint
+    Per RK4 step and source, three-register classical RK4 streams the state 16
+    times: stage 1 reads its input (which is Xn) and writes the accumulator and
+    the next stage input (3), stages 2 and 3 read the stage input, Xn and the
+    accumulator and write the accumulator and the next input (5 each), stage 4
+    reads the stage input and the accumulator and writes Xn (3): 4 n_X per
+    stage on average, n_X = n_hist + 2 n_state; the forward writes and the adjoint
     reads the stage displacement on the closed interior (3 N_int).  Per stage,
     once for all sources: materials and masses (2 N_int + 2 N_nodes), and in
     the adjoint the FP64 gradient accumulators (read and write, 2 N_int).
     """
     nx = n_hist + 2 * sizes.n_state
     nint, nn = sizes.n_int_nodes, sizes.n_nodes
-    per_src = 2 * 4 * es * (5 * nx + 3 * nint)
+    per_src = 2 * 4 * es * (4 * nx + 3 * nint)
     shared = 2 * 4 * es * (2 * nint + 2 * nn) + 4 * 2 * 2 * nint * 8
     return (nsrc * per_src + shared) / (sizes.n_state * nsrc)
 
@@ -155,11 +158,12 @@ def algorithmic_bytes(cls, sizes, prob, nsrc, es):
     nh = history_nodes(prob)
     nint = sizes.n_int_nodes
     if cls == "nodal":
-        # register traffic per RK4 mode, averaged over the 4 stages (0, 1, 1, 2):
-        # mode 0 reads Xn, writes acc and Yout; mode 1 reads Xn and acc, writes
-        # acc and Yout; mode 2 reads acc, writes Xn.  Register comps touched:
-        # 6 per free node, 12 per PML node, 9 more on history nodes.
-        reg = 3.25 * (6.0 * nfree + 12.0 * npml + 9.0 * nh)
+        # register traffic besides the stage input, per RK4 mode, averaged over
+        # the 4 stages (0, 1, 1, 2): mode 0 writes acc and Yout (its input is
+        # Xn itself); mode 1 reads Xn and acc, writes acc and Yout; mode 2 reads
+        # acc, writes Xn.  Register comps touched: 6 per free node, 12 per PML
+        # node, 9 more on history nodes.
+        reg = 3.0 * (6.0 * nfree + 12.0 * npml + 9.0 * nh)
         stage_in = 6.0 * nfree + 12.0 * npml + 9.0 * nh      # Y read by the rate evaluation
         resid = 3.0 * nfree + 6.0 * npml                      # partial array 0
         store = 3.0 * nint                                    # stage displacement kept for the adjoint
