@@ -902,7 +902,7 @@ __device__ __forceinline__ void gather_rows(const Part& P, const PartSlots& S, c
     }
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) out[r] = res[base0 + r] + t[0][r] + t[1][r] + t[2][r];
+  for (int r = 0; r < NR; ++r) out[r] = __builtin_nontemporal_load(&res[base0 + r]) + t[0][r] + t[1][r] + t[2][r];
   if (S.mask == 3 || S.mask == 5 || S.mask == 6 || S.mask == 7) {
 #pragma unroll
     for (int c = 3; c < 8; ++c)
@@ -919,10 +919,10 @@ __device__ __forceinline__ void gather_rows(const Part& P, const PartSlots& S, c
 // STORE = 2 also the PML displacement fields (full gradient).
 // Threads [0, sn) take the displacement rows of node gid (none past n_nodes),
 // threads [sn, sn + n_pml) the PML rows; every load of a thread is issued
-// before its first store.  The accumulator is written and Xn read with
-// non-temporal hints: neither is touched again before the next stage's nodal
-// pass, so they should not displace the stage input and the residual partials
-// that the element kernels and this kernel share in the caches.
+// before its first store.  The accumulator is written, and Xn, the stage
+// input and the residual partials are read, with non-temporal hints: none of
+// them is touched again before the next stage's nodal pass, so they should not
+// displace the stage output that the next element launches read.
 template <typename R, int MODE, int STORE>
 __global__ void __launch_bounds__(PMLFWI_NODAL_THREADS) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
@@ -951,8 +951,8 @@ __global__ void __launch_bounds__(PMLFWI_NODAL_THREADS) nodal_rk_kernel(Geo g, N
     const size_t o1 = u_at(nn, 0, node), o2 = u_at(nn, 3, node);   // x1 u, x2 u of the node
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      u1[d] = Y[o1 + d];
-      u2[d] = Y[o2 + d];
+      u1[d] = __builtin_nontemporal_load(&Y[o1 + d]);
+      u2[d] = __builtin_nontemporal_load(&Y[o2 + d]);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1065,12 +1065,12 @@ __global__ void __launch_bounds__(PMLFWI_NODAL_THREADS) nodal_rk_kernel(Geo g, N
   const size_t b1s = p_at(np, P_X1S, p), b2s = p_at(np, P_X2S, p);
   R s0[6], s1[6], s2[6], rv[6], y1[3];
 #pragma unroll
-  for (int v = 0; v < 6; ++v) s1[v] = PY[b1s + v];
+  for (int v = 0; v < 6; ++v) s1[v] = __builtin_nontemporal_load(&PY[b1s + v]);
 #pragma unroll
-  for (int v = 0; v < 6; ++v) s2[v] = PY[b2s + v];
+  for (int v = 0; v < 6; ++v) s2[v] = __builtin_nontemporal_load(&PY[b2s + v]);
   if (hist) {
 #pragma unroll
-    for (int v = 0; v < 6; ++v) s0[v] = PY[b0s + v];
+    for (int v = 0; v < 6; ++v) s0[v] = __builtin_nontemporal_load(&PY[b0s + v]);
   } else {
 #pragma unroll
     for (int v = 0; v < 6; ++v) s0[v] = R(0);
