@@ -252,7 +252,7 @@ interior_element_kernel(Geo g, const Tile* __restrict__ tiles, int ntiles, int n
       if constexpr (GRAD) {
         const R* F = fwd + (size_t)src * fstride;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sV[d][n] = F[3 * (size_t)mi + d];
+        for (int d = 0; d < 3; ++d) sV[d][n] = __builtin_nontemporal_load(&F[3 * (size_t)mi + d]);
       }
     }
     __syncthreads();
@@ -919,10 +919,11 @@ __device__ __forceinline__ void gather_rows(const Part& P, const PartSlots& S, c
 // STORE = 2 also the PML displacement fields (full gradient).
 // Threads [0, sn) take the displacement rows of node gid (none past n_nodes),
 // threads [sn, sn + n_pml) the PML rows; every load of a thread is issued
-// before its first store.  The accumulator is written, and Xn, the stage
-// input and the residual partials are read, with non-temporal hints: none of
-// them is touched again before the next stage's nodal pass, so they should not
-// displace the stage output that the next element launches read.
+// before its first store.  The accumulator and the kept stage displacement
+// are written, and Xn, the stage input and the residual partials are read,
+// with non-temporal hints: none of them is touched again before the next
+// stage's nodal pass (the kept displacement not before the adjoint), so they
+// should not displace the stage output that the next element launches read.
 template <typename R, int MODE, int STORE>
 __global__ void __launch_bounds__(PMLFWI_NODAL_THREADS) nodal_rk_kernel(Geo g, NodalArgs<R> A) {
   const int src = blockIdx.y;
@@ -1034,7 +1035,7 @@ __global__ void __launch_bounds__(PMLFWI_NODAL_THREADS) nodal_rk_kernel(Geo g, N
       if (mi >= 0) {
         R* S = A.store + (size_t)src * A.store_stride;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) S[3 * (size_t)mi + d] = out1[d];
+        for (int d = 0; d < 3; ++d) __builtin_nontemporal_store(out1[d], &S[3 * (size_t)mi + d]);
       }
     }
     return;
