@@ -64,7 +64,15 @@ class Solver:
             B.fwi_plan_set_loads(self.plan, np.repeat(np.arange(self.nsrc), node.size),
                                  np.tile(node, self.nsrc), np.tile(vec, (self.nsrc, 1)))
         nbytes = int(self.sizes.workspace_bytes)
-        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        try:
+            self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        except torch.cuda.OutOfMemoryError as e:
+            B.fwi_plan_destroy(self.plan)
+            self.plan = None
+            raise MemoryError(
+                f"the workspace of this problem needs {nbytes / 2**30:.1f} GiB of device memory; keep fewer "
+                "stages: ckpt_every = k > 0 stores a full state every k steps and recomputes the "
+                "segment, ckpt_slots bounds the number of stored states") from e
         self.trace_shape = (self.nsrc, self.nsteps + 1, self.nrec, 3)
         self.generation = 0     # bumped by every forward solve (see autograd.py)
 
