@@ -3,6 +3,7 @@
 python -m paper_1504_08340_amd.fwi_run [--nsteps N] [--freqs 4,8,12]
         [--iters K] [--precision fp32|fp64] [--reg tikhonov|tv]
         [--target-frac F] [--start trend|file.npz] [--full-gradient]
+        [--gradient-depth]
 
 Model: three layers (vs 120 / 200 / 300 m/s, boundaries at 5 and 11 m
 depth) and a 4x4x3 m soft block (vs 90 m/s), vp = 2 vs, rho = 2000; nine
@@ -91,6 +92,36 @@ def run(args, wl, S, rho, stages, lam0, mu0, log=sys.stderr):
                 lam_err=err(lam, lt), mu_err=err(mu, mt)), lam, mu
 
 
+def gradient_depth(args, wl, S, rho, stages, log=sys.stdout):
+    """Root mean square, over each depth plane of the interior, of the first
+    stage's misfit gradient of mu at the start model (its L2 representer, the
+    gradient divided by the material mass M~, no regularization) next to that of
+    the model error mu_true - mu_start."""
+    import torch
+
+    import workloads as W
+    from . import binding as B
+    lam0, mu0 = S.tensor(wl.lam), S.tensor(wl.mu)
+    _, wav, obs = stages[0]
+    tr = S.forward(rho, lam0, mu0, wav)
+    _, res = S.misfit(tr, obs)
+    _, gm = S.adjoint_gradient(rho, lam0, mu0, wav, res)
+    mass = torch.empty(S.sizes.n_int_nodes, dtype=torch.float64, device=S.device)
+    B.fwi_material_mass(S.plan, None, mass)
+    rep = (gm / mass).cpu().numpy()
+    err = wl.mu_true - wl.mu
+    ax, ay, az = W.interior_axes(wl.prob)
+    plane = ax.size * ay.size
+    rows = []
+    for jz in range(az.size):
+        sl = slice(jz * plane, (jz + 1) * plane)
+        rows.append(dict(z=float(az[jz]), rms_representer=float(np.sqrt(np.mean(rep[sl] ** 2))),
+                         rms_mu_error=float(np.sqrt(np.mean(err[sl] ** 2)))))
+        print(f"z {az[jz]:6.2f}  rms representer {rows[-1]['rms_representer']:.3e}  "
+              f"rms mu error {rows[-1]['rms_mu_error']:.3e}", file=log, flush=True)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--nsteps", type=int, default=1500)
@@ -102,12 +133,17 @@ def main(argv=None):
     ap.add_argument("--tv-eps", type=float, default=1e10)
     ap.add_argument("--target-frac", type=float, default=1e-2)
     ap.add_argument("--start", default="trend")
+    ap.add_argument("--gradient-depth", action="store_true",
+                    help="print the depth profile of the first stage's gradient at the start model and stop")
     ap.add_argument("--full-gradient", action="store_true",
                     help="chain rule through the material carried into the PML instead of the gradient "
                          "restricted to the interior bricks (Sec. 3.1.3)")
     args = ap.parse_args(argv)
     import torch
     wl, S, rho, stages = build(args)
+    if args.gradient_depth:
+        gradient_depth(args, wl, S, rho, stages)
+        return
     if args.start == "trend":
         lam0, mu0 = S.tensor(wl.lam), S.tensor(wl.mu)
     else:
